@@ -1,0 +1,198 @@
+/*
+ * wsp.h -- C ABI of the MI355X (gfx950) w-stacking w-projection library.
+ *
+ * The library applies the measurement operator of Pratley, Johnston-Hollitt &
+ * McEwen (2019), "w-stacking w-projection hybrid algorithm for wide-field
+ * interferometric imaging", Sec. 3.1, Eqs. (2)-(7):
+ *
+ *     Phi_k = W_k GC_k F Z S~_k,        Phi^dagger y = sum_k Phi_k^dagger y_k,
+ *
+ * with one exact w-projection kernel per visibility (the radial integral of
+ * Eq. (6), evaluated by adaptive Gauss-Kronrod quadrature), w-stacks chosen by
+ * the k-means iteration of Algorithm 1 (Sec. 3.2) after conjugate-symmetry
+ * folding of w < 0 visibilities (Eq. (8), Sec. 3.3).
+ *
+ * Conventions shared by every entry point:
+ *  - image: real N x N, row-major, row j <-> m_j = (j - N/2) dl, column i <->
+ *    l_i = (i - N/2) dl, dl = fov / N; float32 (WSP_FP32_FP64PHASE) or
+ *    float64 (WSP_FP64);
+ *  - visibilities: complex, interleaved (re, im), in the caller's order;
+ *    complex64 or complex128 by precision;
+ *  - uvw: float64 [M][3] in wavelengths, device memory;
+ *  - y = Phi x is the unnormalised operator: pixel values are Jy/pixel and no
+ *    dl dm factor is applied (the paper rescales Phi by the power method);
+ *  - the adjoint returns Re Phi^dagger y (the image is real, Eq. (2)).
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Every call returns a wsp_status: 0 = OK, > 0 = warning, < 0 = error.  No
+ * call throws or aborts.  wsp_last_error() returns a thread-local message for
+ * the last non-zero status.  A context is not thread-safe; separate contexts
+ * may be used concurrently on separate streams.
+ *
+ * Memory ownership: wsp_set_uvw allocates the per-visibility plan (sorted
+ * indices, supports, tap offsets, tile work lists; O(M) bytes) inside the
+ * library and frees it in wsp_destroy.  The three large buffers -- kernel
+ * taps, per-stack Fourier grids and scratch -- are owned by the caller, sized
+ * by wsp_footprint and attached with wsp_bind_memory; they must stay alive
+ * until wsp_destroy or the next bind.
+ */
+#ifndef WSP_H
+#define WSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wsp_status;
+
+#define WSP_OK 0
+#define WSP_WARN_QUAD_MAXEVAL 1   /* some quadrature hit its panel cap       */
+#define WSP_EINVAL -1             /* bad argument or parameter               */
+#define WSP_ENOMEM_BINDING -2     /* memory not bound, or a buffer too small */
+#define WSP_ESUPPORT -3           /* a kernel support exceeds max_support    */
+#define WSP_EHIP -4               /* HIP or hipFFT failure                   */
+#define WSP_ESTATE -5             /* called out of order                     */
+
+#define WSP_FP32_FP64PHASE 0      /* FP32 data and taps, FP64 phase arguments */
+#define WSP_FP64 1                /* FP64 everywhere                          */
+
+typedef struct wsp_params {
+    int32_t n;              /* image side N, even, multiple of 32                       */
+    double oversample;      /* alpha; alpha*N must be an integer multiple of 64         */
+    double fov_rad;         /* full field of view (direction cosine), alpha^2 fov/2 < 1 */
+    int32_t kb_support;     /* J: Kaiser-Bessel support in cells, even, >= 2            */
+    double kb_beta;         /* KB shape; 0 selects 2.34 J                               */
+    double support_scale;   /* f >= 1: J_p = J + 2 ceil(|w - wbar| s f) (see below)     */
+    int32_t n_stacks;       /* K >= 1 w-stacks                                          */
+    int32_t fold_conjugate; /* 1: fold w < 0 onto w > 0 by Eq. (8)                      */
+    double quad_rel_tol;    /* quadrature tolerances (the paper's value is 1e-6, Sec. 4)*/
+    double quad_abs_tol;    /*   both relative to the visibility's kernel peak          */
+    int32_t quad_max_panels;/* cap on quadrature panels per visibility (8..1024)       */
+    int32_t max_support;    /* cap on J_p; larger supports give WSP_ESUPPORT            */
+    int32_t precision;      /* WSP_FP32_FP64PHASE or WSP_FP64                           */
+    double kmeans_tol;      /* Algorithm 1 convergence (the paper uses 1e-3, Sec. 4)    */
+    int32_t kmeans_max_iter;/* iteration cap of Algorithm 1                             */
+    int32_t device;         /* HIP device ordinal                                       */
+} wsp_params;
+
+typedef struct wsp_ctx wsp_ctx;
+
+/* Fill *p with defaults: alpha 2, J 4, beta 2.34 J, f 1, K 1, no fold,
+ * tolerances 1e-6, 1024 panels, max support 1024, FP32+FP64 phase, k-means
+ * tolerance 1e-3 and 100 iterations, device 0.  n and fov_rad are left 0. */
+void wsp_default_params(wsp_params *p);
+
+/* Validate *p and create a context on p->device.  Builds the batched 2-D FFT
+ * plan of the K stacks (G x G, G = alpha N) without allocating its work area.
+ * Errors: WSP_EINVAL (parameters), WSP_EHIP. */
+wsp_status wsp_create(const wsp_params *p, wsp_ctx **out);
+
+/* Attach M visibilities.  uvw: device float64 [M][3] (wavelengths); weights:
+ * device float64 [M] or NULL (all ones).  Both are copied.  Runs, on the
+ * stream, folding (Eq. (8)), the k-means w-stacking of Algorithm 1, the
+ * support rule, the sort by (stack, grid tile) and the tile work lists, and
+ * returns when they are complete.  Support rule (the paper only says supports
+ * shrink with |w - wbar|, Sec. 3.1): J_p = J + 2 ceil(|w_p - wbar_k| s f),
+ * s = rho_c / (n_c du), rho_c = fov sqrt(1/2), n_c = sqrt(1 - rho_c^2),
+ * du = 1 / (alpha fov).  Any previous binding is dropped.
+ * Errors: WSP_EINVAL (M <= 0, non-finite uvw), WSP_ESUPPORT, WSP_EHIP. */
+wsp_status wsp_set_uvw(wsp_ctx *ctx, const double *uvw, int64_t m,
+                       const double *weights, void *stream);
+
+/* Replace the stack assignment (host arrays: labels int32 [M] in caller order,
+ * values in [0, K); centres float64 [K]) and re-plan.  Lets two
+ * implementations share one assignment where Algorithm 1 has ties.  Any
+ * previous binding is dropped.  Errors: WSP_ESTATE, WSP_EINVAL, WSP_ESUPPORT. */
+wsp_status wsp_set_stacks(wsp_ctx *ctx, const int32_t *labels, const double *centres,
+                          void *stream);
+
+/* Copy out the stack assignment (host: labels [M] in caller order or NULL,
+ * centres [K]) and the number of k-means iterations run (0 after
+ * wsp_set_stacks).  Errors: WSP_ESTATE. */
+wsp_status wsp_get_stacks(const wsp_ctx *ctx, int32_t *labels, double *centres,
+                          int32_t *iterations);
+
+/* Copy out per-visibility supports J_p (host int32 [M], caller order) and the
+ * fold flags (host uint8 [M] or NULL).  Errors: WSP_ESTATE. */
+wsp_status wsp_get_support(const wsp_ctx *ctx, int32_t *jp, uint8_t *folded);
+
+/* Exact byte sizes of the caller-owned buffers after wsp_set_uvw:
+ * kernel taps (sum_p J_p^2 complex values), the K Fourier grids (K G^2
+ * complex values) and scratch (degrid partial sums + FFT work area).
+ * Errors: WSP_ESTATE. */
+wsp_status wsp_footprint(const wsp_ctx *ctx, size_t *kernel_bytes,
+                         size_t *grid_bytes, size_t *scratch_bytes);
+
+/* Attach caller-owned device buffers (256-byte aligned) of at least the
+ * footprint sizes.  The library only uses them.  Errors: WSP_ESTATE,
+ * WSP_ENOMEM_BINDING (NULL or too small), WSP_EINVAL (misaligned). */
+wsp_status wsp_bind_memory(wsp_ctx *ctx, void *kernels, size_t kernel_bytes,
+                           void *grids, size_t grid_bytes,
+                           void *scratch, size_t scratch_bytes);
+
+/* Build every visibility's J_p x J_p taps (Eq. (5) and (6)):
+ *   K_p[row, col] = 2 pi int_0^{alpha/2} g(r) exp(-2 pi i w_eff (n(r) - 1))
+ *                   J0(2 pi r q) r dr,
+ * q = |(u_p, v_p)/du - (U0 + col, V0 + row)|, U0 = floor(u_p/du) - J_p/2 + 1,
+ * g = 2-D Fourier transform of the radial KB blob, by adaptive Gauss-Kronrod
+ * (7, 15) quadrature with the tolerances of the parameters.  Blocks until
+ * complete.  Returns WSP_WARN_QUAD_MAXEVAL if a visibility reached
+ * quad_max_panels.  Errors: WSP_ESTATE, WSP_ENOMEM_BINDING, WSP_EHIP. */
+wsp_status wsp_build_kernels(wsp_ctx *ctx, void *stream);
+
+/* Quadrature statistics of the last build: total panels, and visibilities
+ * whose panel cap was reached.  Errors: WSP_ESTATE. */
+wsp_status wsp_quad_stats(const wsp_ctx *ctx, int64_t *panels, int64_t *capped);
+
+/* y = Phi x (Eq. (2)-(5)): per stack, taper and w-bar chirp (S~_k), zero pad
+ * (Z), forward FFT (F), then the sparse convolution with the built taps (GC_k)
+ * and the weights (W_k); folded visibilities are conjugated (Eq. (8)).
+ * image: device real [N][N]; vis: device complex [M] (caller order),
+ * overwritten.  Asynchronous on the stream.  Errors: WSP_ESTATE, WSP_EINVAL,
+ * WSP_EHIP. */
+wsp_status wsp_degrid(wsp_ctx *ctx, const void *image, void *vis, void *stream);
+
+/* image = Re Phi^dagger vis (Eq. (7)): gridding with the conjugated taps,
+ * inverse FFT, crop, conjugate stack correction, real part, summed over
+ * stacks.  vis: device complex [M] (caller order); image: device real [N][N],
+ * overwritten.  Asynchronous on the stream.  Errors as wsp_degrid. */
+wsp_status wsp_grid(wsp_ctx *ctx, const void *vis, void *image, void *stream);
+
+/* Test hook: copy the taps of visibility p (caller order) to host memory
+ * (complex, J_p^2 values, row-major [row][col], rows along v) and return J_p
+ * and the unwrapped base indices U0, V0.  out may be NULL to query J_p only.
+ * Synchronises the device.  Errors: WSP_ESTATE, WSP_EINVAL. */
+wsp_status wsp_kernel_values(wsp_ctx *ctx, int64_t p, void *out, int32_t *jp,
+                             int32_t *u0, int32_t *v0);
+
+/* Per-stage timing of wsp_degrid / wsp_grid with HIP events recorded on the
+ * call's stream around each launch.  wsp_set_timing(ctx, 1) resets the totals
+ * and starts recording, 0 stops.  wsp_stage_times waits for the recorded
+ * events and returns the summed milliseconds and launch counts per stage
+ * (WSP_NSTAGES entries each, in the order of the WSP_STAGE_* indices).
+ * counts may be NULL.  Errors: WSP_EINVAL. */
+#define WSP_NSTAGES 7
+#define WSP_STAGE_TAPER_PAD 0     /* S~_k and Z                      */
+#define WSP_STAGE_FFT_FORWARD 1   /* F, all stacks                   */
+#define WSP_STAGE_DEGRID 2        /* GC_k and W_k                    */
+#define WSP_STAGE_ZERO 3          /* clearing the grids              */
+#define WSP_STAGE_GRID 4          /* W_k and GC_k^dagger             */
+#define WSP_STAGE_FFT_INVERSE 5   /* F^dagger, all stacks            */
+#define WSP_STAGE_CROP_UNTAPER 6  /* Z^dagger, S~_k^dagger, Re, sum  */
+wsp_status wsp_set_timing(wsp_ctx *ctx, int32_t enable);
+wsp_status wsp_stage_times(wsp_ctx *ctx, double *ms, int64_t *counts);
+
+/* Free the library-owned plan and FFT plan.  Does not touch bound buffers. */
+void wsp_destroy(wsp_ctx *ctx);
+
+/* Thread-local description of the last non-zero status. */
+const char *wsp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSP_H */

@@ -1,0 +1,519 @@
+// Host side of the C ABI declared in include/wsp.h: parameter validation,
+// the k-means loop of Algorithm 1, buffer binding and the launch sequence.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wsp_internal.h"
+
+using namespace wsp;
+
+namespace {
+
+thread_local std::string g_err;
+
+wsp_status fail(wsp_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+wsp_status hip_fail(hipError_t e, const char *where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return WSP_EHIP;
+}
+
+#define HIP_OR_FAIL(expr, where)                      \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+double bessel_i0(double x) {
+    // I0(x) = sum_k (x^2/4)^k / (k!)^2
+    double y = 0.25 * x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 400; ++k) {
+        term *= y / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+void free_caller(Plan &pl) {
+    hipFree(pl.u);
+    hipFree(pl.v);
+    hipFree(pl.w);
+    hipFree(pl.wt_in);
+    hipFree(pl.flag);
+    hipFree(pl.label);
+    pl.u = pl.v = pl.w = pl.wt_in = nullptr;
+    pl.flag = nullptr;
+    pl.label = nullptr;
+}
+
+void free_sorted(Plan &pl) {
+    void *ptrs[] = {pl.perm, pl.ux, pl.vx, pl.weff, pl.wt, pl.jp, pl.u0w, pl.v0w,
+                    pl.stack, pl.sflag, pl.tap_off, pl.border, pl.stats};
+    for (void *q : ptrs) hipFree(q);
+    pl.perm = nullptr;
+    pl.ux = pl.vx = pl.weff = pl.wt = nullptr;
+    pl.jp = pl.u0w = pl.v0w = pl.stack = pl.border = nullptr;
+    pl.sflag = nullptr;
+    pl.tap_off = nullptr;
+    pl.stats = nullptr;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
+    int support_err = 0;
+    hipError_t e = make_plan(c, c->plan_centres, s, &support_err);
+    if (e != hipSuccess) return hip_fail(e, "planning");
+    if (support_err & 1) {
+        c->planned = false;
+        return fail(WSP_ESUPPORT, "a kernel support J_p exceeds max_support");
+    }
+    if (support_err & 2) {
+        c->planned = false;
+        return fail(WSP_EINVAL, "a visibility lies beyond 1e9 grid cells");
+    }
+    c->planned = true;
+    c->bound = false;
+    c->built = false;
+    return WSP_OK;
+}
+
+}  // namespace
+
+size_t wsp::cplx_bytes(const wsp_ctx *c) { return c->p.precision == WSP_FP64 ? 16 : 8; }
+
+hipEvent_t wsp::stage_begin(wsp_ctx *c, hipStream_t s) {
+    if (!c->timer.enabled) return nullptr;
+    hipEvent_t ev = nullptr;
+    if (!c->timer.pool.empty()) {
+        ev = c->timer.pool.back();
+        c->timer.pool.pop_back();
+    } else if (hipEventCreate(&ev) != hipSuccess) {
+        return nullptr;
+    }
+    hipEventRecord(ev, s);
+    return ev;
+}
+
+void wsp::stage_end(wsp_ctx *c, int stage, hipEvent_t start, hipStream_t s) {
+    if (!start) return;
+    hipEvent_t ev = nullptr;
+    if (!c->timer.pool.empty()) {
+        ev = c->timer.pool.back();
+        c->timer.pool.pop_back();
+    } else if (hipEventCreate(&ev) != hipSuccess) {
+        c->timer.pool.push_back(start);
+        return;
+    }
+    hipEventRecord(ev, s);
+    c->timer.pending[stage].emplace_back(start, ev);
+}
+
+namespace {
+void drain_timer(wsp_ctx *c) {
+    for (int st = 0; st < kNumStages; ++st) {
+        for (auto &pr : c->timer.pending[st]) {
+            float ms = 0.0f;
+            if (hipEventSynchronize(pr.second) == hipSuccess &&
+                hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+                c->timer.ms[st] += ms;
+                c->timer.count[st] += 1;
+            }
+            c->timer.pool.push_back(pr.first);
+            c->timer.pool.push_back(pr.second);
+        }
+        c->timer.pending[st].clear();
+    }
+}
+}  // namespace
+
+extern "C" {
+
+void wsp_default_params(wsp_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->oversample = 2.0;
+    p->kb_support = 4;
+    p->kb_beta = 0.0;
+    p->support_scale = 1.0;
+    p->n_stacks = 1;
+    p->fold_conjugate = 0;
+    p->quad_rel_tol = 1e-6;
+    p->quad_abs_tol = 1e-6;
+    p->quad_max_panels = kMaxPanels;
+    p->max_support = 1024;
+    p->precision = WSP_FP32_FP64PHASE;
+    p->kmeans_tol = 1e-3;
+    p->kmeans_max_iter = 100;
+    p->device = 0;
+}
+
+const char *wsp_last_error(void) { return g_err.c_str(); }
+
+wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
+    if (!pp || !out) return fail(WSP_EINVAL, "null argument");
+    *out = nullptr;
+    const wsp_params &p = *pp;
+    if (p.n < 2 || p.n % 2) return fail(WSP_EINVAL, "n must be even and >= 2");
+    if (!(p.oversample >= 1.0) || !std::isfinite(p.oversample))
+        return fail(WSP_EINVAL, "oversample must be >= 1");
+    double gd = p.oversample * p.n;
+    long G = std::lround(gd);
+    if (std::fabs(gd - (double)G) > 1e-9 || G % kTile || G > (1L << 20))
+        return fail(WSP_EINVAL, "oversample * n must be an integer multiple of 64 (<= 2^20)");
+    if (!(p.fov_rad > 0.0) || !std::isfinite(p.fov_rad))
+        return fail(WSP_EINVAL, "fov_rad must be positive");
+    if (!(p.oversample * p.oversample * p.fov_rad / 2.0 < 1.0))
+        return fail(WSP_EINVAL, "oversample^2 fov / 2 must be < 1 (kernel integral past the horizon)");
+    if (p.kb_support < 2 || p.kb_support % 2 || p.kb_support > 32)
+        return fail(WSP_EINVAL, "kb_support must be even in [2, 32]");
+    if (!(p.kb_beta >= 0.0) || !std::isfinite(p.kb_beta)) return fail(WSP_EINVAL, "kb_beta must be >= 0");
+    if (!(p.support_scale >= 1.0) || !std::isfinite(p.support_scale))
+        return fail(WSP_EINVAL, "support_scale must be >= 1");
+    if (p.n_stacks < 1 || p.n_stacks > 256) return fail(WSP_EINVAL, "n_stacks must be in [1, 256]");
+    if (p.fold_conjugate != 0 && p.fold_conjugate != 1)
+        return fail(WSP_EINVAL, "fold_conjugate must be 0 or 1");
+    if (!(p.quad_rel_tol >= 0.0) || !(p.quad_abs_tol >= 0.0) ||
+        !(p.quad_rel_tol > 0.0 || p.quad_abs_tol > 0.0) || !std::isfinite(p.quad_rel_tol) ||
+        !std::isfinite(p.quad_abs_tol))
+        return fail(WSP_EINVAL, "quadrature tolerances must be >= 0 and not both 0");
+    if (p.quad_max_panels < 8 || p.quad_max_panels > kMaxPanels)
+        return fail(WSP_EINVAL, "quad_max_panels must be in [8, 1024]");
+    if (p.max_support < p.kb_support || p.max_support > 8192)
+        return fail(WSP_EINVAL, "max_support must be in [kb_support, 8192]");
+    if (p.precision != WSP_FP32_FP64PHASE && p.precision != WSP_FP64)
+        return fail(WSP_EINVAL, "unknown precision");
+    if (!(p.kmeans_tol >= 0.0) || p.kmeans_max_iter < 1)
+        return fail(WSP_EINVAL, "kmeans_tol must be >= 0 and kmeans_max_iter >= 1");
+    if (p.device < 0) return fail(WSP_EINVAL, "device must be >= 0");
+
+    Geom g{};
+    g.n = p.n;
+    g.G = (int)G;
+    g.J = p.kb_support;
+    g.n_stacks = p.n_stacks;
+    g.fov = p.fov_rad;
+    g.alpha = p.oversample;
+    g.inv_du = p.oversample * p.fov_rad;
+    g.du = 1.0 / (p.oversample * p.fov_rad);
+    g.dl = p.fov_rad / p.n;
+    g.r_max = 0.5 * p.oversample;
+    g.beta = p.kb_beta > 0.0 ? p.kb_beta : 2.34 * p.kb_support;
+    g.a = 0.5 * p.kb_support;
+    g.taper_norm = 2.0 * M_PI * g.a * g.a / bessel_i0(g.beta);
+    double rho_c = p.fov_rad * std::sqrt(0.5);
+    double n_c = std::sqrt(1.0 - rho_c * rho_c);
+    g.slope = (rho_c / (n_c * g.du)) * p.support_scale;
+    double xr = 2.0 * M_PI * g.a * g.r_max;
+    double ymax = std::fmax(0.25 * g.beta * g.beta, std::fabs(0.25 * (g.beta * g.beta - xr * xr)));
+    int terms = (int)std::ceil(2.0 * std::sqrt(ymax)) + 30;
+    if (terms > 128) return fail(WSP_EINVAL, "kb_beta too large for the taper series");
+    g.taper_terms = terms;
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (p.device >= ndev) return fail(WSP_EINVAL, "no such device");
+    HIP_OR_FAIL(hipSetDevice(p.device), "hipSetDevice");
+
+    wsp_ctx *c = new (std::nothrow) wsp_ctx();
+    if (!c) return fail(WSP_EHIP, "out of host memory");
+    c->p = p;
+    c->g = g;
+    c->device = p.device;
+    if (hipfftCreate(&c->fft) != HIPFFT_SUCCESS) {
+        delete c;
+        return fail(WSP_EHIP, "hipfftCreate failed");
+    }
+    c->fft_made = true;
+    hipfftSetAutoAllocation(c->fft, 0);
+    int dims[2] = {g.G, g.G};
+    size_t work = 0;
+    hipfftResult r = hipfftMakePlanMany(c->fft, 2, dims, nullptr, 1, g.G * g.G, nullptr, 1,
+                                        g.G * g.G, p.precision == WSP_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C,
+                                        g.n_stacks, &work);
+    if (r != HIPFFT_SUCCESS) {
+        hipfftDestroy(c->fft);
+        delete c;
+        return fail(WSP_EHIP, "hipfftMakePlanMany failed (" + std::to_string((int)r) + ")");
+    }
+    c->fft_work = work;
+    e = hipMalloc(&c->plan_centres, sizeof(double) * g.n_stacks);
+    if (e != hipSuccess) {
+        hipfftDestroy(c->fft);
+        delete c;
+        return hip_fail(e, "hipMalloc centres");
+    }
+    *out = c;
+    return WSP_OK;
+}
+
+wsp_status wsp_set_uvw(wsp_ctx *c, const double *uvw, int64_t m, const double *weights,
+                       void *stream) {
+    if (!c || !uvw) return fail(WSP_EINVAL, "null argument");
+    if (m <= 0 || m > 0x7FFFFFF0LL) return fail(WSP_EINVAL, "m must be in [1, 2^31)");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = as_stream(stream);
+    Plan &pl = c->plan;
+    free_sorted(pl);
+    free_caller(pl);
+    c->planned = c->bound = c->built = false;
+    pl.m = m;
+    HIP_OR_FAIL(hipMalloc(&pl.u, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(hipMalloc(&pl.v, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(hipMalloc(&pl.w, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(hipMalloc(&pl.wt_in, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(hipMalloc(&pl.flag, m), "hipMalloc");
+    HIP_OR_FAIL(hipMalloc(&pl.label, sizeof(int32_t) * m), "hipMalloc");
+    int *d_bad = nullptr;
+    HIP_OR_FAIL(hipMalloc(&d_bad, sizeof(int)), "hipMalloc");
+    hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_fold(uvw, weights, m, c->p.fold_conjugate, pl, d_bad, s);
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(d_bad);
+    if (e != hipSuccess) return hip_fail(e, "fold");
+    if (bad) return fail(WSP_EINVAL, "non-finite uvw or weight");
+
+    // Algorithm 1 (k-means w-stacking), convergence read on the host
+    double wmin = 0, wmax = 0;
+    e = minmax_w(pl, &wmin, &wmax, s);
+    if (e != hipSuccess) return hip_fail(e, "w range");
+    const int K = c->g.n_stacks;
+    std::vector<double> cen(K), nw(K);
+    if (K == 1) {
+        cen[0] = 0.5 * (wmin + wmax);
+    } else {
+        double step = (wmax - wmin) / (double)(K - 1);
+        for (int q = 0; q < K; ++q) cen[q] = (double)q * step + wmin;
+        cen[K - 1] = wmax;
+    }
+    const double floor_ = 1e-12 * std::fmax(wmax - wmin, 1.0);
+    int it = 0;
+    for (it = 1; it <= c->p.kmeans_max_iter; ++it) {
+        HIP_OR_FAIL(hipMemcpyAsync(c->plan_centres, cen.data(), sizeof(double) * K,
+                                   hipMemcpyHostToDevice, s), "centres");
+        e = kmeans_iteration(pl, c->plan_centres, K, nw.data(), s);
+        if (e != hipSuccess) return hip_fail(e, "k-means");
+        double rel = 0.0;
+        for (int q = 0; q < K; ++q)
+            rel += std::fabs(nw[q] - cen[q]) / std::fmax(std::fabs(nw[q]), floor_);
+        rel /= (double)K;
+        cen = nw;
+        if (rel < c->p.kmeans_tol) break;
+    }
+    if (it > c->p.kmeans_max_iter) it = c->p.kmeans_max_iter;
+    c->iterations = it;
+    c->centres = cen;
+    HIP_OR_FAIL(hipMemcpyAsync(c->plan_centres, cen.data(), sizeof(double) * K,
+                               hipMemcpyHostToDevice, s), "centres");
+    return finish_plan(c, s);
+}
+
+wsp_status wsp_set_stacks(wsp_ctx *c, const int32_t *labels, const double *centres, void *stream) {
+    if (!c || !labels || !centres) return fail(WSP_EINVAL, "null argument");
+    if (!c->plan.u) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    const int K = c->g.n_stacks;
+    for (int64_t i = 0; i < c->plan.m; ++i)
+        if (labels[i] < 0 || labels[i] >= K) return fail(WSP_EINVAL, "label out of range");
+    for (int q = 0; q < K; ++q)
+        if (!std::isfinite(centres[q])) return fail(WSP_EINVAL, "non-finite centre");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(hipMemcpyAsync(c->plan.label, labels, sizeof(int32_t) * c->plan.m,
+                               hipMemcpyHostToDevice, s), "labels");
+    HIP_OR_FAIL(hipMemcpyAsync(c->plan_centres, centres, sizeof(double) * K,
+                               hipMemcpyHostToDevice, s), "centres");
+    c->centres.assign(centres, centres + K);
+    c->iterations = 0;
+    return finish_plan(c, s);
+}
+
+wsp_status wsp_get_stacks(const wsp_ctx *c, int32_t *labels, double *centres, int32_t *iterations) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "no plan");
+    if (labels) {
+        HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+        HIP_OR_FAIL(hipMemcpy(labels, c->plan.label, sizeof(int32_t) * c->plan.m,
+                              hipMemcpyDeviceToHost), "labels");
+    }
+    if (centres) std::memcpy(centres, c->centres.data(), sizeof(double) * c->centres.size());
+    if (iterations) *iterations = c->iterations;
+    return WSP_OK;
+}
+
+wsp_status wsp_get_support(const wsp_ctx *c, int32_t *jp, uint8_t *folded) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "no plan");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    const int64_t m = c->plan.m;
+    if (jp) {
+        std::vector<int32_t> js(m), perm(m);
+        HIP_OR_FAIL(hipMemcpy(js.data(), c->plan.jp, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "jp");
+        HIP_OR_FAIL(hipMemcpy(perm.data(), c->plan.perm, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "perm");
+        for (int64_t i = 0; i < m; ++i) jp[perm[i]] = js[i];
+    }
+    if (folded) HIP_OR_FAIL(hipMemcpy(folded, c->plan.flag, m, hipMemcpyDeviceToHost), "flags");
+    return WSP_OK;
+}
+
+wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_bytes,
+                         size_t *scratch_bytes) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    const size_t cb = cplx_bytes(c);
+    if (kernel_bytes) *kernel_bytes = (size_t)c->plan.total_taps * cb;
+    if (grid_bytes) *grid_bytes = (size_t)c->g.G * c->g.G * c->g.n_stacks * cb;
+    if (scratch_bytes) *scratch_bytes = c->fft_work;
+    return WSP_OK;
+}
+
+wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void *grids,
+                           size_t grid_bytes, void *scratch, size_t scratch_bytes) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    size_t kb = 0, gb = 0, sb = 0;
+    wsp_footprint(c, &kb, &gb, &sb);
+    if (!kernels || !grids || (sb > 0 && !scratch))
+        return fail(WSP_ENOMEM_BINDING, "null buffer");
+    if (kernel_bytes < kb || grid_bytes < gb || scratch_bytes < sb)
+        return fail(WSP_ENOMEM_BINDING, "buffer smaller than wsp_footprint");
+    if (((uintptr_t)kernels | (uintptr_t)grids | (uintptr_t)scratch) & 255u)
+        return fail(WSP_EINVAL, "buffers must be 256-byte aligned");
+    if (sb > 0 && hipfftSetWorkArea(c->fft, scratch) != HIPFFT_SUCCESS)
+        return fail(WSP_EHIP, "hipfftSetWorkArea failed");
+    c->taps = kernels;
+    c->taps_bytes = kernel_bytes;
+    c->grids = grids;
+    c->grid_bytes = grid_bytes;
+    c->scratch = scratch;
+    c->scratch_bytes = scratch_bytes;
+    c->bound = true;
+    c->built = false;
+    return WSP_OK;
+}
+
+wsp_status wsp_build_kernels(wsp_ctx *c, void *stream) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    if (!c->bound) return fail(WSP_ENOMEM_BINDING, "wsp_bind_memory first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(launch_build(c, s), "build");
+    unsigned long long st[2] = {0, 0};
+    HIP_OR_FAIL(hipMemcpyAsync(st, c->plan.stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats");
+    HIP_OR_FAIL(hipStreamSynchronize(s), "build");
+    c->quad_panels = (int64_t)st[0];
+    c->quad_capped = (int64_t)st[1];
+    c->built = true;
+    if (st[1] > 0) {
+        g_err = std::to_string(st[1]) + " visibilities reached quad_max_panels";
+        return WSP_WARN_QUAD_MAXEVAL;
+    }
+    return WSP_OK;
+}
+
+wsp_status wsp_quad_stats(const wsp_ctx *c, int64_t *panels, int64_t *capped) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->built) return fail(WSP_ESTATE, "no build yet");
+    if (panels) *panels = c->quad_panels;
+    if (capped) *capped = c->quad_capped;
+    return WSP_OK;
+}
+
+wsp_status wsp_degrid(wsp_ctx *c, const void *image, void *vis, void *stream) {
+    if (!c || !image || !vis) return fail(WSP_EINVAL, "null argument");
+    if (!c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    HIP_OR_FAIL(run_degrid(c, image, vis, as_stream(stream)), "degrid");
+    return WSP_OK;
+}
+
+wsp_status wsp_grid(wsp_ctx *c, const void *vis, void *image, void *stream) {
+    if (!c || !image || !vis) return fail(WSP_EINVAL, "null argument");
+    if (!c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    HIP_OR_FAIL(run_grid(c, vis, image, as_stream(stream)), "grid");
+    return WSP_OK;
+}
+
+wsp_status wsp_kernel_values(wsp_ctx *c, int64_t p, void *out, int32_t *jp, int32_t *u0,
+                             int32_t *v0) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "no plan");
+    if (out && !c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    if (p < 0 || p >= c->plan.m) return fail(WSP_EINVAL, "visibility index out of range");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    HIP_OR_FAIL(hipDeviceSynchronize(), "sync");
+    const int64_t m = c->plan.m;
+    std::vector<int32_t> perm(m);
+    HIP_OR_FAIL(hipMemcpy(perm.data(), c->plan.perm, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "perm");
+    int64_t sidx = -1;
+    for (int64_t i = 0; i < m; ++i)
+        if (perm[i] == p) {
+            sidx = i;
+            break;
+        }
+    if (sidx < 0) return fail(WSP_EHIP, "permutation lookup failed");
+    int32_t j = 0;
+    int64_t off = 0;
+    double uu = 0, vv = 0;
+    HIP_OR_FAIL(hipMemcpy(&j, c->plan.jp + sidx, sizeof(int32_t), hipMemcpyDeviceToHost), "jp");
+    HIP_OR_FAIL(hipMemcpy(&off, c->plan.tap_off + sidx, sizeof(int64_t), hipMemcpyDeviceToHost), "off");
+    HIP_OR_FAIL(hipMemcpy(&uu, c->plan.u + p, sizeof(double), hipMemcpyDeviceToHost), "u");
+    HIP_OR_FAIL(hipMemcpy(&vv, c->plan.v + p, sizeof(double), hipMemcpyDeviceToHost), "v");
+    if (jp) *jp = j;
+    if (u0) *u0 = (int32_t)((int64_t)std::floor(uu * c->g.inv_du) - j / 2 + 1);
+    if (v0) *v0 = (int32_t)((int64_t)std::floor(vv * c->g.inv_du) - j / 2 + 1);
+    if (out) {
+        const size_t cb = cplx_bytes(c);
+        HIP_OR_FAIL(hipMemcpy(out, (const char *)c->taps + off * cb, (size_t)j * j * cb,
+                              hipMemcpyDeviceToHost), "taps");
+    }
+    return WSP_OK;
+}
+
+wsp_status wsp_set_timing(wsp_ctx *c, int32_t enable) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    drain_timer(c);
+    for (int st = 0; st < kNumStages; ++st) {
+        c->timer.ms[st] = 0.0;
+        c->timer.count[st] = 0;
+    }
+    c->timer.enabled = enable != 0;
+    return WSP_OK;
+}
+
+wsp_status wsp_stage_times(wsp_ctx *c, double *ms, int64_t *counts) {
+    if (!c || !ms) return fail(WSP_EINVAL, "null argument");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    drain_timer(c);
+    for (int st = 0; st < kNumStages; ++st) {
+        ms[st] = c->timer.ms[st];
+        if (counts) counts[st] = c->timer.count[st];
+    }
+    return WSP_OK;
+}
+
+void wsp_destroy(wsp_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    drain_timer(c);
+    for (hipEvent_t ev : c->timer.pool) hipEventDestroy(ev);
+    free_sorted(c->plan);
+    free_caller(c->plan);
+    hipFree(c->plan_centres);
+    if (c->fft_made) hipfftDestroy(c->fft);
+    delete c;
+}
+
+}  // extern "C"

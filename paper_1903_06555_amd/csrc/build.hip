@@ -1,0 +1,467 @@
+// Kernel builder: one exact w-projection kernel per visibility (Eqs. (5), (6)).
+//
+//   K_p[row, col] = 2 pi int_0^{alpha/2} g(r) e^{-2 pi i w_eff (n(r) - 1)} J0(2 pi r q) r dr
+//
+// Visibilities are processed costliest first, in batches: phase 1 runs one
+// wavefront per visibility, phase 2 one wavefront per chunk of 512 taps.
+//
+// Phase 1 (adaptive partition, FP64).  The integrand differs between taps
+// only through J0(2 pi r q), so all J_p^2 taps share one panel partition.
+// The initial partition holds about one cycle of the integrand's phase bound
+// |w| (1 - n(r)) + q_max r per panel.  Each panel is integrated by the
+// Gauss-Kronrod (7, 15) pair at kProbes distances q_j spanning [0, q_max];
+// its error estimate is max_j |K15_j - G7_j|.  A panel of width h is accepted
+// when the estimate is <= tol S h / R, with S the largest |K(q_j)| after the
+// first pass (so the panel estimates add up to at most tol S), otherwise it
+// is bisected; rounds repeat until every panel passes or the panel cap is
+// reached.  Probes are evaluated in FP64 so the estimate is not swamped by
+// FP32 rounding.
+//
+// Phase 2 (taps).  Every tap is integrated with the 15-point Kronrod rule on
+// the final partition.  FP32 path: node values g(r) r e^{...} in FP64, cast to
+// FP32; J0 in FP32 with its phase reduced in FP64; per-panel-group partial
+// sums in FP32, accumulated over the partition in FP64.  FP64 path: all FP64.
+#include <hipcub/hipcub.hpp>
+
+#include "wsp_devmath.h"
+
+namespace wsp {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kTapsPerLane = 8;
+constexpr int kPanelGroup = 4;                 // panels per node batch (60 of 64 lanes)
+constexpr int kGroupNodes = kPanelGroup * WSP_GK_N;
+constexpr int64_t kBuildBatch = 65536;    // visibilities per partition batch
+
+struct BuildArgs {
+    const int32_t *border;
+    int64_t m;
+    const double *ux, *vx, *weff;
+    const int32_t *jp;
+    const int64_t *tap_off;
+    void *taps;
+    Geom g;
+    double tol;
+    int max_panels;
+    unsigned long long *stats;
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Integrand phase bound (cycles): |w| (1 - n(r)) + q_max r, increasing in r.
+__device__ __forceinline__ double phase_bound(double r, double aw, double qmax, const Geom &g) {
+    double rho = r * g.inv_du;
+    return aw * (-n_minus_one(rho * rho)) + qmax * r;
+}
+
+// Node value 2 pi r g(r) e^{-2 pi i w (n - 1)} in FP64.
+__device__ __forceinline__ void node_value(double r, double weff, const Geom &g, double *re,
+                                           double *im) {
+    double rho = r * g.inv_du;
+    double f = reduce_rev(-weff * n_minus_one(rho * rho));
+    double sn, cs;
+    sincospi(2.0 * f, &sn, &cs);
+    double amp = kTwoPi * r * taper_g(r, g);
+    *re = amp * cs;
+    *im = amp * sn;
+}
+
+// G7/K15 on panel [a, b] at the probe distances; returns the error estimate
+// and (if acc) adds the K15 values into sre/sim.
+__device__ float eval_panel_probes(double a, double b, double weff, double qstep, const Geom &g,
+                                   double *sre, double *sim, bool acc) {
+    double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+    double kr[kProbes], ki[kProbes], gr[kProbes], gi[kProbes];
+#pragma unroll
+    for (int j = 0; j < kProbes; ++j) kr[j] = ki[j] = gr[j] = gi[j] = 0.0;
+    for (int n = 0; n < WSP_GK_N; ++n) {
+        double r = fma(half, wsp_gk_x[n], mid);
+        double are, aim;
+        node_value(r, weff, g, &are, &aim);
+        double wk = wsp_gk_wk[n], wg = wsp_gk_wg[n];
+#pragma unroll
+        for (int j = 0; j < kProbes; ++j) {
+            double J = j0(kTwoPi * r * (qstep * j));
+            double tr = are * J, ti = aim * J;
+            kr[j] = fma(wk, tr, kr[j]);
+            ki[j] = fma(wk, ti, ki[j]);
+            gr[j] = fma(wg, tr, gr[j]);
+            gi[j] = fma(wg, ti, gi[j]);
+        }
+    }
+    double err = 0.0;
+#pragma unroll
+    for (int j = 0; j < kProbes; ++j) {
+        double dr = kr[j] - gr[j], di = ki[j] - gi[j];
+        err = fmax(err, half * sqrt(dr * dr + di * di));
+        if (acc) {
+            sre[j] += half * kr[j];
+            sim[j] += half * ki[j];
+        }
+    }
+    return (float)err;
+}
+
+// Phase 1.  Returns the panel count; the partition ends up in *out (LDS), as
+// |bnd[0]| < |bnd[1]| < ... < |bnd[P]|.
+__device__ int adaptive_partition(float *bA, float *bB, float **out, double weff, double qmax,
+                                  const BuildArgs &A, int lane, bool *capped) {
+    const Geom &g = A.g;
+    const double R = g.r_max;
+    const double aw = fabs(weff);
+    const int cap = A.max_panels;
+    double phiR = phase_bound(R, aw, qmax, g);
+    int P = (int)ceil(phiR);
+    P = P < 2 ? 2 : (P > cap / 2 ? cap / 2 : P);
+    // initial boundaries at equal steps of the phase bound (bisection in FP64);
+    // negative sign = panel starting here still has to be evaluated
+    for (int i = lane; i <= P; i += kWave) {
+        float val;
+        if (i == 0) {
+            val = 0.0f;
+        } else if (i == P) {
+            val = (float)R;
+        } else {
+            double target = phiR * (double)i / (double)P;
+            double lo = 0.0, hi = R;
+            for (int it = 0; it < 48; ++it) {
+                double midr = 0.5 * (lo + hi);
+                if (phase_bound(midr, aw, qmax, g) < target) lo = midr;
+                else hi = midr;
+            }
+            val = (float)(0.5 * (lo + hi));
+        }
+        bA[i] = (i < P) ? -val : val;
+    }
+    wave_sync();
+    float *cur = bA, *oth = bB;
+    const double qstep = qmax / (double)(kProbes - 1);
+    double sre[kProbes], sim[kProbes];
+#pragma unroll
+    for (int j = 0; j < kProbes; ++j) sre[j] = sim[j] = 0.0;
+    double thr = 0.0;
+    *capped = false;
+    constexpr int kChunks = kMaxPanels / kWave;
+    for (int round = 0; round < 32; ++round) {
+        float err[kChunks];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            err[c] = -1.0f;
+            int i = c * kWave + lane;
+            if (c * kWave < P && i < P) {
+                float fa = cur[i];
+                if (signbit(fa)) {
+                    err[c] = eval_panel_probes((double)fabsf(fa), (double)fabsf(cur[i + 1]), weff,
+                                               qstep, g, sre, sim, round == 0);
+                }
+            }
+        }
+        if (round == 0) {
+            double S = 0.0;
+#pragma unroll
+            for (int j = 0; j < kProbes; ++j) {
+                double re = wave_sum(sre[j]), im = wave_sum(sim[j]);
+                S = fmax(S, sqrt(re * re + im * im));
+            }
+            thr = A.tol * S / R;
+        }
+        // count the panels to split
+        int total = 0;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            if (c * kWave < P) {
+                int i = c * kWave + lane;
+                bool sp = false;
+                if (i < P && err[c] >= 0.0f) {
+                    float wa = fabsf(cur[i]), wb = fabsf(cur[i + 1]);
+                    sp = (double)err[c] > thr * (double)(wb - wa) && (wb - wa) > 4.0e-6f * wb;
+                }
+                total += __popcll(__ballot(sp));
+            }
+        }
+        if (total == 0) break;
+        if (P + total > cap) {
+            *capped = true;
+            break;
+        }
+        // rebuild the boundary list with the midpoints inserted
+        int run = 0;
+#pragma unroll
+        for (int c = 0; c <= kChunks; ++c) {
+            if (c * kWave <= P) {
+                int i = c * kWave + lane;
+                bool sp = false;
+                float wa = 0.0f, wb = 0.0f;
+                if (i < P && c < kChunks && err[c] >= 0.0f) {
+                    wa = fabsf(cur[i]);
+                    wb = fabsf(cur[i + 1]);
+                    sp = (double)err[c] > thr * (double)(wb - wa) && (wb - wa) > 4.0e-6f * wb;
+                }
+                unsigned long long bal = __ballot(sp);
+                int pre = run + __popcll(bal & lanemask_lt(lane));
+                if (i <= P) {
+                    float v = fabsf(cur[i]);
+                    oth[i + pre] = (sp && i < P) ? -v : v;
+                    if (sp) oth[i + pre + 1] = -(0.5f * (wa + wb));
+                }
+                run += __popcll(bal);
+            }
+        }
+        wave_sync();
+        float *t = cur;
+        cur = oth;
+        oth = t;
+        P += total;
+    }
+    *out = cur;
+    return P;
+}
+
+// Phase 1 kernel: one wavefront per visibility of the batch; writes the
+// final partition (|boundaries|) and its panel count.
+__global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, int nb,
+                                                   float *part, int *npan) {
+    __shared__ float s_bnd[kWavesPerBlock][2][kMaxPanels + 2];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int i = blockIdx.x * kWavesPerBlock + wid;
+    if (i >= nb) return;  // whole wave leaves; no block-wide barriers below
+    const int p = A.border[batch0 + i];
+    const double ux = A.ux[p], vx = A.vx[p], weff = A.weff[p];
+    const int jp = A.jp[p];
+    double cu = fmax(fabs(ux), fabs(ux - (double)(jp - 1)));
+    double cv = fmax(fabs(vx), fabs(vx - (double)(jp - 1)));
+    double qmax = sqrt(cu * cu + cv * cv);
+    float *bnd = nullptr;
+    bool capped = false;
+    int P = adaptive_partition(s_bnd[wid][0], s_bnd[wid][1], &bnd, weff, qmax, A, lane, &capped);
+    float *dst = part + (int64_t)i * (kMaxPanels + 2);
+    for (int k = lane; k <= P; k += kWave) dst[k] = fabsf(bnd[k]);
+    if (lane == 0) {
+        npan[i] = P;
+        atomicAdd(&A.stats[0], (unsigned long long)P);
+        if (capped) atomicAdd(&A.stats[1], 1ull);
+    }
+}
+
+// Phase 2 kernel: one wavefront per (visibility, chunk of 64 kTapsPerLane
+// taps); unit_off is the exclusive prefix of chunks per visibility.
+template <bool kFP64>
+__global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int nb,
+                                              const float *__restrict__ part,
+                                              const int *__restrict__ npan,
+                                              const int *__restrict__ unit_off, int nunits) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int unit = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (unit >= nunits) return;
+    // visibility of this unit: last i with unit_off[i] <= unit
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (unit_off[mid] <= unit) lo = mid;
+        else hi = mid - 1;
+    }
+    const int i = lo;
+    const int p = A.border[batch0 + i];
+    const Geom &g = A.g;
+    const double ux = A.ux[p], vx = A.vx[p], weff = A.weff[p];
+    const int jp = A.jp[p];
+    const int64_t off = A.tap_off[p];
+    const int64_t ntap = (int64_t)jp * jp;
+    const int P = npan[i];
+    const float *bnd = part + (int64_t)i * (kMaxPanels + 2);
+    const int64_t chunk = (int64_t)kWave * kTapsPerLane;
+    const int64_t cbase = (int64_t)(unit - unit_off[i]) * chunk;
+
+    double q[kTapsPerLane];
+    float qf[kTapsPerLane];
+    double accr[kTapsPerLane], acci[kTapsPerLane];
+#pragma unroll
+    for (int k = 0; k < kTapsPerLane; ++k) {
+        int64_t t = cbase + (int64_t)k * kWave + lane;
+        int row = (int)(t / jp);
+        int col = (int)(t - (int64_t)row * jp);
+        double du = ux - (double)col, dv = vx - (double)row;
+        q[k] = (t < ntap) ? sqrt(du * du + dv * dv) : 0.0;
+        qf[k] = (float)(kTwoPi * q[k]);
+        accr[k] = acci[k] = 0.0;
+    }
+    for (int pg = 0; pg < P; pg += kPanelGroup) {
+        // node data for kPanelGroup panels: lane = panel * 15 + node
+        double nr = 0.0, nre = 0.0, nim = 0.0;
+        {
+            int pan = pg + lane / WSP_GK_N;
+            int nd = lane % WSP_GK_N;
+            if (lane < kGroupNodes && pan < P) {
+                double a = (double)bnd[pan], b = (double)bnd[pan + 1];
+                double half = 0.5 * (b - a);
+                nr = fma(half, wsp_gk_x[nd], 0.5 * (a + b));
+                node_value(nr, weff, g, &nre, &nim);
+                double wgt = half * wsp_gk_wk[nd];
+                nre *= wgt;
+                nim *= wgt;
+            }
+        }
+        const int nn = (P - pg >= kPanelGroup ? kPanelGroup : P - pg) * WSP_GK_N;
+        if constexpr (kFP64) {
+            double pr[kTapsPerLane], pi_[kTapsPerLane];
+#pragma unroll
+            for (int k = 0; k < kTapsPerLane; ++k) pr[k] = pi_[k] = 0.0;
+            for (int n = 0; n < nn; ++n) {
+                double rn = __shfl(nr, n, kWave);
+                double are = __shfl(nre, n, kWave), aim = __shfl(nim, n, kWave);
+#pragma unroll
+                for (int k = 0; k < kTapsPerLane; ++k) {
+                    if (cbase + (int64_t)k * kWave < ntap) {
+                        double J = j0(kTwoPi * rn * q[k]);
+                        pr[k] = fma(are, J, pr[k]);
+                        pi_[k] = fma(aim, J, pi_[k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kTapsPerLane; ++k) {
+                accr[k] += pr[k];
+                acci[k] += pi_[k];
+            }
+        } else {
+            float nref = (float)nre, nimf = (float)nim;
+            // FP32 partial sums over one panel (15 nodes), accumulated in FP64
+            for (int pb = 0; pb < nn; pb += WSP_GK_N) {
+                float pr[kTapsPerLane], pi_[kTapsPerLane];
+#pragma unroll
+                for (int k = 0; k < kTapsPerLane; ++k) pr[k] = pi_[k] = 0.0f;
+                for (int n = pb; n < pb + WSP_GK_N; ++n) {
+                    double rn = __shfl(nr, n, kWave);
+                    float are = __shfl(nref, n, kWave), aim = __shfl(nimf, n, kWave);
+                    float rnf = (float)rn;
+#pragma unroll
+                    for (int k = 0; k < kTapsPerLane; ++k) {
+                        if (cbase + (int64_t)k * kWave < ntap) {
+                            float J = j0_fp64phase(rn, q[k], rnf * qf[k]);
+                            pr[k] = fmaf(are, J, pr[k]);
+                            pi_[k] = fmaf(aim, J, pi_[k]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kTapsPerLane; ++k) {
+                    accr[k] += (double)pr[k];
+                    acci[k] += (double)pi_[k];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTapsPerLane; ++k) {
+        int64_t t = cbase + (int64_t)k * kWave + lane;
+        if (t < ntap) {
+            if constexpr (kFP64) {
+                ((double2 *)A.taps)[off + t] = make_double2(accr[k], acci[k]);
+            } else {
+                ((float2 *)A.taps)[off + t] = make_float2((float)accr[k], (float)acci[k]);
+            }
+        }
+    }
+}
+
+__global__ void k_unit_counts(const int32_t *__restrict__ border, const int32_t *__restrict__ jp,
+                              int64_t batch0, int nb, int *cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nb) return;
+    if (i == nb) {
+        cnt[i] = 0;
+        return;
+    }
+    int64_t j = jp[border[batch0 + i]];
+    const int64_t chunk = (int64_t)kWave * kTapsPerLane;
+    cnt[i] = (int)((j * j + chunk - 1) / chunk);
+}
+
+}  // namespace
+
+hipError_t launch_build(wsp_ctx *c, hipStream_t s) {
+    BuildArgs A{};
+    const Plan &pl = c->plan;
+    A.border = pl.border;
+    A.m = pl.m;
+    A.ux = pl.ux;
+    A.vx = pl.vx;
+    A.weff = pl.weff;
+    A.jp = pl.jp;
+    A.tap_off = pl.tap_off;
+    A.taps = c->taps;
+    A.g = c->g;
+    A.tol = c->p.quad_abs_tol > 0.0 ? c->p.quad_abs_tol : c->p.quad_rel_tol;
+    A.max_panels = c->p.quad_max_panels;
+    A.stats = pl.stats;
+    hipError_t e = hipMemsetAsync(pl.stats, 0, 2 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    const int B = (int)(pl.m < kBuildBatch ? pl.m : kBuildBatch);
+    float *part = nullptr;
+    int *npan = nullptr, *cnt = nullptr, *uoff = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    auto cleanup = [&]() {
+        hipFree(part);
+        hipFree(npan);
+        hipFree(cnt);
+        hipFree(uoff);
+        hipFree(tmp);
+    };
+#define WSP_BSTEP(expr)        \
+    do {                       \
+        e = (expr);            \
+        if (e != hipSuccess) { \
+            cleanup();         \
+            return e;          \
+        }                      \
+    } while (0)
+    WSP_BSTEP(hipMalloc(&part, sizeof(float) * (size_t)B * (kMaxPanels + 2)));
+    WSP_BSTEP(hipMalloc(&npan, sizeof(int) * (size_t)B));
+    WSP_BSTEP(hipMalloc(&cnt, sizeof(int) * (size_t)(B + 1)));
+    WSP_BSTEP(hipMalloc(&uoff, sizeof(int) * (size_t)(B + 1)));
+    WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, uoff, B + 1, s));
+    WSP_BSTEP(hipMalloc(&tmp, tmp_bytes));
+    for (int64_t b0 = 0; b0 < pl.m; b0 += B) {
+        int nb = (int)(pl.m - b0 < B ? pl.m - b0 : B);
+        dim3 block(kWave * kWavesPerBlock);
+        hipLaunchKernelGGL(k_partition, dim3((nb + kWavesPerBlock - 1) / kWavesPerBlock), block, 0,
+                           s, A, b0, nb, part, npan);
+        hipLaunchKernelGGL(k_unit_counts, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, pl.border,
+                           pl.jp, b0, nb, cnt);
+        WSP_BSTEP(hipGetLastError());
+        WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, uoff, nb + 1, s));
+        int nunits = 0;
+        WSP_BSTEP(hipMemcpyAsync(&nunits, uoff + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+        WSP_BSTEP(hipStreamSynchronize(s));
+        dim3 grid((unsigned)((nunits + kWavesPerBlock - 1) / kWavesPerBlock));
+        if (c->p.precision == WSP_FP64) {
+            hipLaunchKernelGGL(k_taps<true>, grid, block, 0, s, A, b0, nb, part, npan, uoff, nunits);
+        } else {
+            hipLaunchKernelGGL(k_taps<false>, grid, block, 0, s, A, b0, nb, part, npan, uoff, nunits);
+        }
+        WSP_BSTEP(hipGetLastError());
+    }
+    WSP_BSTEP(hipStreamSynchronize(s));
+    cleanup();
+    return hipSuccess;
+#undef WSP_BSTEP
+}
+
+}  // namespace wsp

@@ -1,0 +1,99 @@
+// Device math shared by the kernel builder and the image-domain kernels.
+//
+// Phase arguments (the w-chirp of Eqs. (4) and (6) and the Bessel phase
+// 2 pi r q) are formed and range-reduced in FP64, in revolutions; only the
+// reduced fraction in [-1/2, 1/2] is handed to FP32 polynomials.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wsp_internal.h"
+#include "wsp_tables.h"
+
+namespace wsp {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// g(r): 2-D Fourier transform of the radial Kaiser-Bessel blob (Lewitt's pair,
+// n = 2, m = 0), g(r) = 2 pi a^2 / I0(beta) * I1(z) / z with
+// z^2 = beta^2 - (2 pi a r)^2.  I1(z)/z = 1/2 sum_k y^k / (k! (k+1)!),
+// y = z^2 / 4, is one power series for both signs of z^2 (for z^2 < 0 it is
+// J1(|z|)/|z|), summed in FP64.
+__device__ __forceinline__ double taper_g(double r, const Geom &g) {
+    double x = kTwoPi * g.a * r;
+    double y = 0.25 * (g.beta * g.beta - x * x);
+    double term = 1.0, sum = 1.0;
+    for (int k = 0; k < g.taper_terms; ++k) {
+        term *= y * wsp_series_r[k];
+        sum += term;
+    }
+    return g.taper_norm * 0.5 * sum;
+}
+
+// n - 1 with n = sqrt(1 - rho^2), written as -rho^2 / (1 + n).
+__device__ __forceinline__ double n_minus_one(double rho2) {
+    return -rho2 / (1.0 + sqrt(1.0 - rho2));
+}
+
+// Reduce a phase given in revolutions to [-1/2, 1/2].
+__device__ __forceinline__ double reduce_rev(double s) { return s - rint(s); }
+
+// sin(2 pi f), cos(2 pi f) for |f| <= 1/2 (FP32 polynomials on an octant).
+__device__ __forceinline__ void sincos_rev(float f, float *sn, float *cs) {
+    float k4 = rintf(4.0f * f);
+    float gg = fmaf(-0.25f, k4, f);  // |gg| <= 1/8
+    float g2 = gg * gg;
+    float s = wsp_sin_c[WSP_SC_N - 1];
+    float c = wsp_cos_c[WSP_SC_N - 1];
+#pragma unroll
+    for (int i = WSP_SC_N - 2; i >= 0; --i) {
+        s = fmaf(s, g2, wsp_sin_c[i]);
+        c = fmaf(c, g2, wsp_cos_c[i]);
+    }
+    s *= gg;
+    int q = ((int)k4) & 3;
+    float s1 = (q & 1) ? c : s;
+    float c1 = (q & 1) ? s : c;
+    *sn = (q & 2) ? -s1 : s1;
+    *cs = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// J0(2 pi r q) for the FP32 path.  x < 8: Chebyshev series in FP64 (no
+// transcendental, same issue rate as FP32 on CDNA without packed math);
+// x >= 8: Hankel form in FP32 with the Bessel phase reduced in FP64.
+// xf = 2 pi r q in FP32 (used where relative precision suffices).
+__device__ __forceinline__ float j0_fp64phase(double r, double q, float xf) {
+    if (xf < 8.0f) {
+        // Chebyshev series in u = 2 (x/8)^2 - 1, Clenshaw recurrence
+        double x = kTwoPi * (r * q);
+        double u = fma(x * x, 1.0 / 32.0, -1.0);
+        double u2 = 2.0 * u;
+        double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+        for (int j = WSP_J0S_N - 1; j >= 1; --j) {
+            double b0 = fma(u2, b1, wsp_j0s_c[j] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        return (float)fma(u, b1, wsp_j0s_c[0] - b2);
+    }
+    // Hankel form: sqrt(2/(pi x)) (P0 cos(x - pi/4) - Q0 sin(x - pi/4));
+    // (x - pi/4) / (2 pi) = r q - 1/8 revolutions, reduced in FP64.
+    float f = (float)reduce_rev(fma(r, q, -0.125));
+    float sn, cs;
+    sincos_rev(f, &sn, &cs);
+    float inv = 8.0f / xf;
+    float t = inv * inv;
+    float P = wsp_j0l_p[WSP_J0L_N - 1];
+    float Q = wsp_j0l_q[WSP_J0L_N - 1];
+#pragma unroll
+    for (int i = WSP_J0L_N - 2; i >= 0; --i) {
+        P = fmaf(P, t, wsp_j0l_p[i]);
+        Q = fmaf(Q, t, wsp_j0l_q[i]);
+    }
+    Q *= inv;
+    float amp = 0.79788456080286535588f * rsqrtf(xf);  // sqrt(2/pi) / sqrt(x)
+    return amp * (P * cs - Q * sn);
+}
+
+}  // namespace wsp

@@ -1,0 +1,128 @@
+// Internal declarations shared by the host API and the HIP kernels of libwsp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wsp.h"
+
+namespace wsp {
+
+constexpr int kWave = 64;
+constexpr int kTile = 64;          // grid tile side (cells) used for sort keys
+constexpr int kMaxPanels = 1024;   // quadrature panels per visibility (LDS bound)
+constexpr int kProbes = 8;         // probe distances used by the panel error estimate
+
+// Geometry of one operator, all derived once on the host (FP64).
+struct Geom {
+    int n;               // image side N
+    int G;               // grid side alpha N
+    int J;               // KB support
+    int n_stacks;        // K
+    int taper_terms;     // terms of the FP64 series of g
+    double fov;          // radians
+    double alpha;
+    double inv_du;       // alpha fov: wavelengths -> grid cells
+    double du;           // 1 / (alpha fov)
+    double dl;           // fov / N
+    double r_max;        // alpha / 2 (cycles per cell)
+    double beta;         // KB shape
+    double a;            // J / 2
+    double taper_norm;   // 2 pi a^2 / I0(beta)
+    double slope;        // support slope s f (cells per wavelength of |w - wbar|)
+};
+
+// Library-owned, per-visibility plan.  "Caller" arrays are in the caller's
+// order; the others are in sorted (stack, tile) order.
+struct Plan {
+    int64_t m = 0;
+    // caller order
+    double *u = nullptr, *v = nullptr, *w = nullptr;   // folded coordinates
+    double *wt_in = nullptr;                            // weights (ones if none given)
+    uint8_t *flag = nullptr;                            // folded
+    int32_t *label = nullptr;                           // stack
+    // sorted order
+    int32_t *perm = nullptr;      // sorted -> caller index
+    double *ux = nullptr;         // u/du - U0 (offset of the visibility from its first tap)
+    double *vx = nullptr;
+    double *weff = nullptr;       // w - wbar_k
+    double *wt = nullptr;         // weight
+    int32_t *jp = nullptr;        // support
+    int32_t *u0w = nullptr;       // first tap column, wrapped into [0, G)
+    int32_t *v0w = nullptr;
+    int32_t *stack = nullptr;
+    uint8_t *sflag = nullptr;
+    int64_t *tap_off = nullptr;   // [m + 1] prefix of jp^2
+    int32_t *border = nullptr;    // build order: sorted indices, costliest first
+    unsigned long long *stats = nullptr;  // [0] panels, [1] capped visibilities
+    int64_t total_taps = 0;
+    int32_t max_jp = 0;
+};
+
+// Stages timed with HIP events when timing is enabled (wsp_set_timing).
+enum Stage { kStTaperPad = 0, kStFftForward, kStDegrid, kStZero, kStGrid, kStFftInverse,
+             kStCropUntaper, kNumStages };
+
+struct StageTimer {
+    bool enabled = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kNumStages];
+    std::vector<hipEvent_t> pool;
+    double ms[kNumStages] = {};
+    int64_t count[kNumStages] = {};
+};
+
+}  // namespace wsp
+
+struct wsp_ctx {
+    wsp_params p{};
+    wsp::Geom g{};
+    int device = 0;
+    hipfftHandle fft = 0;
+    bool fft_made = false;
+    size_t fft_work = 0;
+    wsp::Plan plan;
+    bool planned = false;
+    std::vector<double> centres;   // host copy of the stack centres
+    double *plan_centres = nullptr; // device copy
+    int iterations = 0;
+    void *taps = nullptr;
+    size_t taps_bytes = 0;
+    void *grids = nullptr;
+    size_t grid_bytes = 0;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    bool bound = false;
+    bool built = false;
+    int64_t quad_panels = 0;
+    int64_t quad_capped = 0;
+    wsp::StageTimer timer;
+};
+
+namespace wsp {
+
+size_t cplx_bytes(const wsp_ctx *c);
+
+// plan.hip
+hipError_t launch_fold(const double *uvw, const double *wts, int64_t m, int fold,
+                       Plan &pl, int *d_bad, hipStream_t s);
+hipError_t minmax_w(const Plan &pl, double *wmin, double *wmax, hipStream_t s);
+hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K,
+                            double *h_new_centres, hipStream_t s);
+hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err);
+
+// build.hip
+hipError_t launch_build(wsp_ctx *c, hipStream_t s);
+
+// api.cpp: stage timing around one launch (no-ops when timing is off)
+hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);
+void stage_end(wsp_ctx *c, int stage, hipEvent_t start, hipStream_t s);
+
+// apply.hip
+hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s);
+hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s);
+
+}  // namespace wsp

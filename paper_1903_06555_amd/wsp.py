@@ -1,0 +1,346 @@
+"""Python binding of libwsp (ctypes).  Argument marshalling only.
+
+Every step of the operator runs in the HIP library; PyTorch supplies device
+memory and streams.  Module-level functions mirror the C ABI in
+``include/wsp.h`` one to one (``wsp_create``, ``wsp_set_uvw``, ...);
+:class:`Operator` strings them together for the common case.
+
+There is no fallback: if ``libwsp.so`` is missing or cannot be loaded the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwsp.so")
+
+WSP_OK = 0
+WSP_WARN_QUAD_MAXEVAL = 1
+WSP_EINVAL = -1
+WSP_ENOMEM_BINDING = -2
+WSP_ESUPPORT = -3
+WSP_EHIP = -4
+WSP_ESTATE = -5
+
+WSP_FP32_FP64PHASE = 0
+WSP_FP64 = 1
+
+PRECISIONS = {"fp32_fp64phase": WSP_FP32_FP64PHASE, "fp64": WSP_FP64}
+
+EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
+            "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
+            "wsp_build_kernels", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
+            "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
+            "wsp_last_error")
+
+STAGES = ("taper_pad", "fft_forward", "degrid", "zero", "grid", "fft_inverse", "crop_untaper")
+
+
+class wsp_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("oversample", ctypes.c_double),
+        ("fov_rad", ctypes.c_double),
+        ("kb_support", ctypes.c_int32),
+        ("kb_beta", ctypes.c_double),
+        ("support_scale", ctypes.c_double),
+        ("n_stacks", ctypes.c_int32),
+        ("fold_conjugate", ctypes.c_int32),
+        ("quad_rel_tol", ctypes.c_double),
+        ("quad_abs_tol", ctypes.c_double),
+        ("quad_max_panels", ctypes.c_int32),
+        ("max_support", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("kmeans_tol", ctypes.c_double),
+        ("kmeans_max_iter", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class WspError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"wsp status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libwsp.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "wsp_default_params": (None, [ctypes.POINTER(wsp_params)]),
+        "wsp_create": (i32, [ctypes.POINTER(wsp_params), ctypes.POINTER(P)]),
+        "wsp_set_uvw": (i32, [P, P, i64, P, P]),
+        "wsp_set_stacks": (i32, [P, P, P, P]),
+        "wsp_get_stacks": (i32, [P, P, P, P]),
+        "wsp_get_support": (i32, [P, P, P]),
+        "wsp_footprint": (i32, [P, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
+        "wsp_bind_memory": (i32, [P, P, sz, P, sz, P, sz]),
+        "wsp_build_kernels": (i32, [P, P]),
+        "wsp_quad_stats": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "wsp_degrid": (i32, [P, P, P, P]),
+        "wsp_grid": (i32, [P, P, P, P]),
+        "wsp_kernel_values": (i32, [P, i64, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)]),
+        "wsp_set_timing": (i32, [P, i32]),
+        "wsp_stage_times": (i32, [P, P, P]),
+        "wsp_destroy": (None, [P]),
+        "wsp_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise WspError(status, load_library().wsp_last_error().decode())
+    if status > 0:
+        warnings.warn(f"wsp warning {status}: {load_library().wsp_last_error().decode()}")
+    return status
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return t.data_ptr()
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    raise TypeError(type(t))
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ---- one-to-one wrappers of the C ABI ---------------------------------------
+
+def wsp_default_params() -> wsp_params:
+    p = wsp_params()
+    load_library().wsp_default_params(ctypes.byref(p))
+    return p
+
+
+def wsp_create(params: wsp_params) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(load_library().wsp_create(ctypes.byref(params), ctypes.byref(ctx)))
+    return ctx
+
+
+def wsp_set_uvw(ctx, uvw: torch.Tensor, weights: torch.Tensor | None = None, stream=None):
+    _check(load_library().wsp_set_uvw(ctx, _ptr(uvw), uvw.shape[0], _ptr(weights), _stream(stream)))
+
+
+def wsp_set_stacks(ctx, labels: np.ndarray, centres: np.ndarray, stream=None):
+    _check(load_library().wsp_set_stacks(ctx, _ptr(labels), _ptr(centres), _stream(stream)))
+
+
+def wsp_get_stacks(ctx, labels: np.ndarray | None, centres: np.ndarray):
+    it = ctypes.c_int32()
+    _check(load_library().wsp_get_stacks(ctx, _ptr(labels), _ptr(centres), ctypes.byref(it)))
+    return it.value
+
+
+def wsp_get_support(ctx, jp: np.ndarray, folded: np.ndarray | None = None):
+    _check(load_library().wsp_get_support(ctx, _ptr(jp), _ptr(folded)))
+
+
+def wsp_footprint(ctx):
+    k, g, s = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().wsp_footprint(ctx, ctypes.byref(k), ctypes.byref(g), ctypes.byref(s)))
+    return k.value, g.value, s.value
+
+
+def wsp_bind_memory(ctx, kernels: torch.Tensor, grids: torch.Tensor, scratch: torch.Tensor):
+    nb = lambda t: t.numel() * t.element_size()
+    _check(load_library().wsp_bind_memory(ctx, _ptr(kernels), nb(kernels), _ptr(grids), nb(grids),
+                                          _ptr(scratch), nb(scratch)))
+
+
+def wsp_build_kernels(ctx, stream=None) -> int:
+    return _check(load_library().wsp_build_kernels(ctx, _stream(stream)))
+
+
+def wsp_quad_stats(ctx):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().wsp_quad_stats(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def wsp_degrid(ctx, image: torch.Tensor, vis: torch.Tensor, stream=None):
+    _check(load_library().wsp_degrid(ctx, _ptr(image), _ptr(vis), _stream(stream)))
+
+
+def wsp_grid(ctx, vis: torch.Tensor, image: torch.Tensor, stream=None):
+    _check(load_library().wsp_grid(ctx, _ptr(vis), _ptr(image), _stream(stream)))
+
+
+def wsp_kernel_values(ctx, p: int, complex_dtype=np.complex64):
+    L = load_library()
+    jp, u0, v0 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(L.wsp_kernel_values(ctx, p, None, ctypes.byref(jp), ctypes.byref(u0), ctypes.byref(v0)))
+    out = np.empty((jp.value, jp.value), dtype=complex_dtype)
+    _check(L.wsp_kernel_values(ctx, p, _ptr(out), ctypes.byref(jp), ctypes.byref(u0),
+                               ctypes.byref(v0)))
+    return out, u0.value, v0.value
+
+
+def wsp_set_timing(ctx, enable: bool):
+    _check(load_library().wsp_set_timing(ctx, int(bool(enable))))
+
+
+def wsp_stage_times(ctx):
+    """{stage: (total ms, launches)} since the last wsp_set_timing."""
+    ms = np.zeros(len(STAGES))
+    cnt = np.zeros(len(STAGES), dtype=np.int64)
+    _check(load_library().wsp_stage_times(ctx, _ptr(ms), _ptr(cnt)))
+    return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
+
+
+def wsp_destroy(ctx):
+    load_library().wsp_destroy(ctx)
+
+
+def wsp_last_error() -> str:
+    return load_library().wsp_last_error().decode()
+
+
+# ---- convenience ----------------------------------------------------------------
+
+def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: int = 4,
+                kb_beta: float = 0.0, support_scale: float = 1.0, n_stacks: int = 1,
+                fold: bool = False, quad_tol: float = 1e-6, quad_max_panels: int = 1024,
+                max_support: int = 1024, precision: str = "fp32_fp64phase",
+                kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, device: int = 0) -> wsp_params:
+    p = wsp_default_params()
+    p.n = n
+    p.fov_rad = fov_rad
+    p.oversample = oversample
+    p.kb_support = kb_support
+    p.kb_beta = kb_beta
+    p.support_scale = support_scale
+    p.n_stacks = n_stacks
+    p.fold_conjugate = int(bool(fold))
+    p.quad_rel_tol = quad_tol
+    p.quad_abs_tol = quad_tol
+    p.quad_max_panels = quad_max_panels
+    p.max_support = max_support
+    p.precision = PRECISIONS[precision]
+    p.kmeans_tol = kmeans_tol
+    p.kmeans_max_iter = kmeans_max_iter
+    p.device = device
+    return p
+
+
+class Operator:
+    """Phi and Re Phi^dagger for one set of visibilities, kernels resident on the GPU."""
+
+    def __init__(self, params: wsp_params, uvw, weights=None, labels=None, centres=None,
+                 build: bool = True, stream=None):
+        self.params = params
+        self.fp64 = params.precision == WSP_FP64
+        self.real_dtype = torch.float64 if self.fp64 else torch.float32
+        self.complex_dtype = torch.complex128 if self.fp64 else torch.complex64
+        self.device = torch.device("cuda", params.device)
+        self.n = params.n
+        self.ctx = wsp_create(params)
+        self.uvw = torch.as_tensor(np.asarray(uvw, dtype=np.float64)).to(self.device).contiguous()
+        self.m = self.uvw.shape[0]
+        self.weights = (None if weights is None else
+                        torch.as_tensor(np.asarray(weights, dtype=np.float64)).to(self.device).contiguous())
+        wsp_set_uvw(self.ctx, self.uvw, self.weights, stream)
+        if labels is not None:
+            self.set_stacks(labels, centres, stream)
+        self._bind()
+        self.build_status = None
+        if build:
+            self.build(stream)
+
+    def _bind(self):
+        kb, gb, sb = wsp_footprint(self.ctx)
+        self.footprint = {"kernel_bytes": kb, "grid_bytes": gb, "scratch_bytes": sb}
+        self.kernels = torch.empty(max(kb, 256), dtype=torch.uint8, device=self.device)
+        self.grids = torch.empty(max(gb, 256), dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(max(sb, 256), dtype=torch.uint8, device=self.device)
+        wsp_bind_memory(self.ctx, self.kernels, self.grids, self.scratch)
+
+    def set_stacks(self, labels, centres, stream=None):
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        centres = np.ascontiguousarray(centres, dtype=np.float64)
+        wsp_set_stacks(self.ctx, labels, centres, stream)
+        self._bind()
+
+    def build(self, stream=None) -> int:
+        self.build_status = wsp_build_kernels(self.ctx, stream)
+        return self.build_status
+
+    def stacks(self):
+        K = self.params.n_stacks
+        labels = np.empty(self.m, dtype=np.int32)
+        centres = np.empty(K, dtype=np.float64)
+        it = wsp_get_stacks(self.ctx, labels, centres)
+        return labels, centres, it
+
+    def support(self):
+        jp = np.empty(self.m, dtype=np.int32)
+        folded = np.empty(self.m, dtype=np.uint8)
+        wsp_get_support(self.ctx, jp, folded)
+        return jp, folded.astype(bool)
+
+    def quad_stats(self):
+        return wsp_quad_stats(self.ctx)
+
+    def kernel(self, p: int):
+        return wsp_kernel_values(self.ctx, p, np.complex128 if self.fp64 else np.complex64)
+
+    def degrid(self, image: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        image = image.to(self.device, self.real_dtype).contiguous()
+        if image.shape != (self.n, self.n):
+            raise ValueError(f"image must be {self.n}x{self.n}")
+        if out is None:
+            out = torch.empty(self.m, dtype=self.complex_dtype, device=self.device)
+        wsp_degrid(self.ctx, image, out, stream)
+        return out
+
+    def grid(self, vis: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        vis = vis.to(self.device, self.complex_dtype).contiguous()
+        if vis.shape != (self.m,):
+            raise ValueError(f"vis must have {self.m} entries")
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=self.real_dtype, device=self.device)
+        wsp_grid(self.ctx, vis, out, stream)
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            wsp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
