@@ -143,6 +143,13 @@ wsp_status wsp_bind_memory(wsp_ctx *ctx, void *kernels, size_t kernel_bytes,
  * quad_max_panels.  Errors: WSP_ESTATE, WSP_ENOMEM_BINDING, WSP_EHIP. */
 wsp_status wsp_build_kernels(wsp_ctx *ctx, void *stream);
 
+/* The same build for the visibilities first .. first+count-1 of the build
+ * order (costliest first), so a caller can report progress on long builds.
+ * Parts must follow each other from first = 0; the operator is usable once
+ * all M are built.  Errors: as wsp_build_kernels, WSP_EINVAL (range),
+ * WSP_ESTATE (out of order). */
+wsp_status wsp_build_kernels_part(wsp_ctx *ctx, int64_t first, int64_t count, void *stream);
+
 /* Quadrature statistics of the last build: total panels, and visibilities
  * whose panel cap was reached.  Errors: WSP_ESTATE. */
 wsp_status wsp_quad_stats(const wsp_ctx *ctx, int64_t *panels, int64_t *capped);

@@ -82,6 +82,7 @@ wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
     c->planned = true;
     c->bound = false;
     c->built = false;
+    c->built_upto = 0;
     return WSP_OK;
 }
 
@@ -398,27 +399,39 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
     c->scratch_bytes = scratch_bytes;
     c->bound = true;
     c->built = false;
+    c->built_upto = 0;
+    return WSP_OK;
+}
+
+wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void *stream) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    if (!c->bound) return fail(WSP_ENOMEM_BINDING, "wsp_bind_memory first");
+    if (first != c->built_upto) return fail(WSP_ESTATE, "parts must be built in order from 0");
+    if (count <= 0 || first + count > c->plan.m) return fail(WSP_EINVAL, "bad visibility range");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(launch_build(c, first, count, s), "build");
+    unsigned long long st[2] = {0, 0};
+    HIP_OR_FAIL(hipMemcpyAsync(st, c->plan.stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats");
+    HIP_OR_FAIL(hipStreamSynchronize(s), "build");
+    c->quad_panels = (int64_t)st[0];
+    c->quad_capped = (int64_t)st[1];
+    c->built_upto = first + count;
+    c->built = c->built_upto == c->plan.m;
+    if (st[1] > 0) {
+        g_err = std::to_string(st[1]) + " visibilities reached quad_max_panels";
+        return WSP_WARN_QUAD_MAXEVAL;
+    }
     return WSP_OK;
 }
 
 wsp_status wsp_build_kernels(wsp_ctx *c, void *stream) {
     if (!c) return fail(WSP_EINVAL, "null argument");
     if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
-    if (!c->bound) return fail(WSP_ENOMEM_BINDING, "wsp_bind_memory first");
-    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
-    hipStream_t s = as_stream(stream);
-    HIP_OR_FAIL(launch_build(c, s), "build");
-    unsigned long long st[2] = {0, 0};
-    HIP_OR_FAIL(hipMemcpyAsync(st, c->plan.stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats");
-    HIP_OR_FAIL(hipStreamSynchronize(s), "build");
-    c->quad_panels = (int64_t)st[0];
-    c->quad_capped = (int64_t)st[1];
-    c->built = true;
-    if (st[1] > 0) {
-        g_err = std::to_string(st[1]) + " visibilities reached quad_max_panels";
-        return WSP_WARN_QUAD_MAXEVAL;
-    }
-    return WSP_OK;
+    c->built_upto = 0;
+    c->built = false;
+    return wsp_build_kernels_part(c, 0, c->plan.m, stream);
 }
 
 wsp_status wsp_quad_stats(const wsp_ctx *c, int64_t *panels, int64_t *capped) {

@@ -395,7 +395,7 @@ __global__ void k_unit_counts(const int32_t *__restrict__ border, const int32_t 
 
 }  // namespace
 
-hipError_t launch_build(wsp_ctx *c, hipStream_t s) {
+hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s) {
     BuildArgs A{};
     const Plan &pl = c->plan;
     A.border = pl.border;
@@ -410,9 +410,13 @@ hipError_t launch_build(wsp_ctx *c, hipStream_t s) {
     A.tol = c->p.quad_abs_tol > 0.0 ? c->p.quad_abs_tol : c->p.quad_rel_tol;
     A.max_panels = c->p.quad_max_panels;
     A.stats = pl.stats;
-    hipError_t e = hipMemsetAsync(pl.stats, 0, 2 * sizeof(unsigned long long), s);
-    if (e != hipSuccess) return e;
-    const int B = (int)(pl.m < kBuildBatch ? pl.m : kBuildBatch);
+    hipError_t e = hipSuccess;
+    if (first == 0) {
+        e = hipMemsetAsync(pl.stats, 0, 2 * sizeof(unsigned long long), s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t end = first + count;
+    const int B = (int)(count < kBuildBatch ? count : kBuildBatch);
     float *part = nullptr;
     int *npan = nullptr, *cnt = nullptr, *uoff = nullptr;
     void *tmp = nullptr;
@@ -438,8 +442,8 @@ hipError_t launch_build(wsp_ctx *c, hipStream_t s) {
     WSP_BSTEP(hipMalloc(&uoff, sizeof(int) * (size_t)(B + 1)));
     WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, uoff, B + 1, s));
     WSP_BSTEP(hipMalloc(&tmp, tmp_bytes));
-    for (int64_t b0 = 0; b0 < pl.m; b0 += B) {
-        int nb = (int)(pl.m - b0 < B ? pl.m - b0 : B);
+    for (int64_t b0 = first; b0 < end; b0 += B) {
+        int nb = (int)(end - b0 < B ? end - b0 : B);
         dim3 block(kWave * kWavesPerBlock);
         hipLaunchKernelGGL(k_partition, dim3((nb + kWavesPerBlock - 1) / kWavesPerBlock), block, 0,
                            s, A, b0, nb, part, npan);

@@ -97,6 +97,7 @@ struct wsp_ctx {
     size_t scratch_bytes = 0;
     bool bound = false;
     bool built = false;
+    int64_t built_upto = 0;         // visibilities built so far, in build order
     int64_t quad_panels = 0;
     int64_t quad_capped = 0;
     wsp::StageTimer timer;
@@ -115,7 +116,7 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K,
 hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err);
 
 // build.hip
-hipError_t launch_build(wsp_ctx *c, hipStream_t s);
+hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s);
 
 // api.cpp: stage timing around one launch (no-ops when timing is off)
 hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);

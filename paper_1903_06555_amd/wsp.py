@@ -35,7 +35,7 @@ PRECISIONS = {"fp32_fp64phase": WSP_FP32_FP64PHASE, "fp64": WSP_FP64}
 
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
             "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
-            "wsp_build_kernels", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
+            "wsp_build_kernels", "wsp_build_kernels_part", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
             "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
             "wsp_last_error")
 
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "wsp_footprint": (i32, [P, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "wsp_bind_memory": (i32, [P, P, sz, P, sz, P, sz]),
         "wsp_build_kernels": (i32, [P, P]),
+        "wsp_build_kernels_part": (i32, [P, i64, i64, P]),
         "wsp_quad_stats": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "wsp_degrid": (i32, [P, P, P, P]),
         "wsp_grid": (i32, [P, P, P, P]),
@@ -182,6 +183,10 @@ def wsp_bind_memory(ctx, kernels: torch.Tensor, grids: torch.Tensor, scratch: to
 
 def wsp_build_kernels(ctx, stream=None) -> int:
     return _check(load_library().wsp_build_kernels(ctx, _stream(stream)))
+
+
+def wsp_build_kernels_part(ctx, first: int, count: int, stream=None) -> int:
+    return _check(load_library().wsp_build_kernels_part(ctx, first, count, _stream(stream)))
 
 
 def wsp_quad_stats(ctx):
@@ -293,9 +298,20 @@ class Operator:
         wsp_set_stacks(self.ctx, labels, centres, stream)
         self._bind()
 
-    def build(self, stream=None) -> int:
-        self.build_status = wsp_build_kernels(self.ctx, stream)
-        return self.build_status
+    def build(self, stream=None, part: int | None = None, progress=None) -> int:
+        """Build all kernels; with ``part``, in slices of that many visibilities,
+        calling ``progress(done, total)`` after each."""
+        if part is None:
+            self.build_status = wsp_build_kernels(self.ctx, stream)
+            return self.build_status
+        status = 0
+        for first in range(0, self.m, part):
+            cnt = min(part, self.m - first)
+            status = max(status, wsp_build_kernels_part(self.ctx, first, cnt, stream))
+            if progress is not None:
+                progress(first + cnt, self.m)
+        self.build_status = status
+        return status
 
     def stacks(self):
         K = self.params.n_stacks
