@@ -53,17 +53,7 @@ void free_caller(Plan &pl) {
     pl.label = nullptr;
 }
 
-void free_sorted(Plan &pl) {
-    void *ptrs[] = {pl.perm, pl.ux, pl.vx, pl.weff, pl.wt, pl.jp, pl.u0w, pl.v0w,
-                    pl.stack, pl.sflag, pl.tap_off, pl.border, pl.stats};
-    for (void *q : ptrs) hipFree(q);
-    pl.perm = nullptr;
-    pl.ux = pl.vx = pl.weff = pl.wt = nullptr;
-    pl.jp = pl.u0w = pl.v0w = pl.stack = pl.border = nullptr;
-    pl.sflag = nullptr;
-    pl.tap_off = nullptr;
-    pl.stats = nullptr;
-}
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -263,7 +253,7 @@ wsp_status wsp_set_uvw(wsp_ctx *c, const double *uvw, int64_t m, const double *w
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = as_stream(stream);
     Plan &pl = c->plan;
-    free_sorted(pl);
+    free_sorted_plan(pl);
     free_caller(pl);
     c->planned = c->bound = c->built = false;
     pl.m = m;
@@ -373,7 +363,9 @@ wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_by
     const size_t cb = cplx_bytes(c);
     if (kernel_bytes) *kernel_bytes = (size_t)c->plan.total_taps * cb;
     if (grid_bytes) *grid_bytes = (size_t)c->g.G * c->g.G * c->g.n_stacks * cb;
-    if (scratch_bytes) *scratch_bytes = c->fft_work;
+    if (scratch_bytes)
+        *scratch_bytes = align256(c->fft_work) + align256((size_t)c->plan.m * cb) +
+                         (size_t)c->plan.n_multi * kTile * kTile * cb;
     return WSP_OK;
 }
 
@@ -389,8 +381,10 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
         return fail(WSP_ENOMEM_BINDING, "buffer smaller than wsp_footprint");
     if (((uintptr_t)kernels | (uintptr_t)grids | (uintptr_t)scratch) & 255u)
         return fail(WSP_EINVAL, "buffers must be 256-byte aligned");
-    if (sb > 0 && hipfftSetWorkArea(c->fft, scratch) != HIPFFT_SUCCESS)
+    if (c->fft_work > 0 && hipfftSetWorkArea(c->fft, scratch) != HIPFFT_SUCCESS)
         return fail(WSP_EHIP, "hipfftSetWorkArea failed");
+    c->scratch_yw = (char *)scratch + align256(c->fft_work);
+    c->scratch_part = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
     c->taps = kernels;
     c->taps_bytes = kernel_bytes;
     c->grids = grids;
@@ -522,7 +516,7 @@ void wsp_destroy(wsp_ctx *c) {
     hipSetDevice(c->device);
     drain_timer(c);
     for (hipEvent_t ev : c->timer.pool) hipEventDestroy(ev);
-    free_sorted(c->plan);
+    free_sorted_plan(c->plan);
     free_caller(c->plan);
     hipFree(c->plan_centres);
     if (c->fft_made) hipfftDestroy(c->fft);

@@ -145,15 +145,23 @@ __device__ __forceinline__ R wave_sum_r(R x) {
     return x;
 }
 
-// GC_k, W_k: one wavefront per visibility (sorted order), lanes over taps.
+// GC_k, W_k: one wavefront per visibility, lanes over taps.  Waves are
+// mapped XCD-aware: each of the 8 XCDs takes a contiguous run of the sorted
+// visibilities, so the grid region it gathers from stays in its own L2.  Tap
+// coordinates advance incrementally (no division in the loop).
 template <bool kFP64>
 __global__ __launch_bounds__(256) void k_degrid(const typename Types<kFP64>::C *__restrict__ taps,
                                                 const typename Types<kFP64>::C *__restrict__ grids,
                                                 typename Types<kFP64>::C *vis, ApplyArgs a) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
+    constexpr int kU = 4;  // taps per lane in flight
     const int lane = threadIdx.x & 63;
-    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nblk = gridDim.x;
+    const int per = nblk / 8;  // gridDim.x is a multiple of 8
+    const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    // wave-uniform visibility index (metadata through the scalar cache)
+    const int64_t p = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
     if (p >= a.m) return;
     const int G = a.g.G;
     const int jp = a.jp[p];
@@ -161,14 +169,40 @@ __global__ __launch_bounds__(256) void k_degrid(const typename Types<kFP64>::C *
     const C *tp = taps + a.tap_off[p];
     const C *gk = grids + (int64_t)a.stack[p] * G * G;
     const int ntap = jp * jp;
+    // lane's first tap (t = lane) and the per-step advance of 64 taps
+    int row = lane / jp, col = lane - (lane / jp) * jp;
+    const int drow = 64 / jp, dcol = 64 - (64 / jp) * jp;
+    int V = v0 + row;
+    while (V >= G) V -= G;
     R ar = 0, ai = 0;
-    for (int t = lane; t < ntap; t += 64) {
-        int row = t / jp, col = t - row * jp;
-        int V = wrap_index(v0 + row, G), U = wrap_index(u0 + col, G);
-        C K = tp[t];
-        C z = gk[(int64_t)V * G + U];
-        ar += K.x * z.x - K.y * z.y;
-        ai += K.x * z.y + K.y * z.x;
+    for (int t0 = 0; t0 < ntap; t0 += 64 * kU) {
+        C K[kU], z[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int t = t0 + 64 * u + lane;
+            int U = u0 + col;
+            while (U >= G) U -= G;
+            if (t < ntap) {
+                K[u] = tp[t];
+                z[u] = gk[(int64_t)V * G + U];
+            } else {
+                K[u].x = K[u].y = 0;
+                z[u].x = z[u].y = 0;
+            }
+            col += dcol;
+            int dr = drow;
+            if (col >= jp) {
+                col -= jp;
+                ++dr;
+            }
+            V += dr;
+            while (V >= G) V -= G;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            ar += K[u].x * z[u].x - K[u].y * z[u].y;
+            ai += K[u].x * z[u].y + K[u].y * z[u].x;
+        }
     }
     ar = wave_sum_r(ar);
     ai = wave_sum_r(ai);
@@ -181,32 +215,171 @@ __global__ __launch_bounds__(256) void k_degrid(const typename Types<kFP64>::C *
     }
 }
 
-// GC_k^dagger, W_k: one wavefront per visibility, conj(K) y added with atomics.
+// W_k and Eq. (8) on the adjoint's input: yw[p] = W_p (conj) y[perm[p]] in
+// sorted order.
 template <bool kFP64>
-__global__ __launch_bounds__(256) void k_grid(const typename Types<kFP64>::C *__restrict__ taps,
-                                              const typename Types<kFP64>::C *__restrict__ vis,
-                                              typename Types<kFP64>::C *grids, ApplyArgs a) {
+__global__ void k_prep_vis(const typename Types<kFP64>::C *__restrict__ vis,
+                           typename Types<kFP64>::C *yw, ApplyArgs a) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    const int lane = threadIdx.x & 63;
-    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.m) return;
-    const int G = a.g.G;
-    const int jp = a.jp[p];
-    const int u0 = a.u0w[p], v0 = a.v0w[p];
-    const C *tp = taps + a.tap_off[p];
-    C *gk = grids + (int64_t)a.stack[p] * G * G;
     C y = vis[a.perm[p]];
     R w = (R)a.wt[p];
-    R yr = y.x * w, yi = (a.sflag[p] ? -y.y : y.y) * w;
-    const int ntap = jp * jp;
-    for (int t = lane; t < ntap; t += 64) {
-        int row = t / jp, col = t - row * jp;
-        int V = wrap_index(v0 + row, G), U = wrap_index(u0 + col, G);
-        C K = tp[t];
-        R *dst = (R *)(gk + (int64_t)V * G + U);
-        atomicAdd(dst, K.x * yr + K.y * yi);
-        atomicAdd(dst + 1, K.x * yi - K.y * yr);
+    C o;
+    o.x = y.x * w;
+    o.y = (a.sflag[p] ? -y.y : y.y) * w;
+    yw[p] = o;
+}
+
+struct TileArgs {
+    const int4 *ent;
+    const int32_t *ent_sorted;
+    const int32_t *item_start;
+    const uint32_t *item_key;
+    const uint8_t *item_sole;
+    const int32_t *item_slot;
+    void *partial;
+    const int32_t *jp;
+    const int64_t *tap_off;
+    int n_items;
+    int tile_bits;
+    int G;
+};
+
+// XCD-aware block order: consecutive items (neighbouring tiles) go to the
+// same XCD, which dispatches blocks round-robin over its 8 dies.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int nx = 8;
+    int per = (n + nx - 1) / nx;
+    return (b % nx) * per + b / nx;
+}
+
+// GC_k^dagger: one block per work item (a run of entries of one grid tile).
+// The tile is privatised in LDS; the four wavefronts take entries in turn,
+// lanes walk the entry's tap sub-block and add conj(K) yw with LDS atomics;
+// the tile is then stored (its only item) or added atomically to the grid.
+template <bool kFP64>
+__global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+                                                    const typename Types<kFP64>::C *__restrict__ yw,
+                                                    typename Types<kFP64>::C *grids, TileArgs t) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    constexpr int kChunk = 256;  // entries whose metadata is staged in LDS at a time
+    constexpr int kU = 8;        // taps per lane in flight
+    __shared__ R tre[kTile * kTile];
+    __shared__ R tim[kTile * kTile];
+    __shared__ int4 s_ent[kChunk];
+    __shared__ int64_t s_off[kChunk];
+    __shared__ int s_jp[kChunk];
+    __shared__ C s_y[kChunk];
+    const int item = xcd_item(blockIdx.x, t.n_items);
+    if (item >= t.n_items) return;  // uniform over the block
+    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+        tre[i] = 0;
+        tim[i] = 0;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
+    for (int base = s_beg; base < s_end; base += kChunk) {
+        const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
+        __syncthreads();  // LDS tile cleared / previous chunk consumed
+        if ((int)threadIdx.x < n) {
+            const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
+            s_ent[threadIdx.x] = en;
+            s_off[threadIdx.x] = t.tap_off[en.x];
+            s_jp[threadIdx.x] = t.jp[en.x];
+            s_y[threadIdx.x] = yw[en.x];
+        }
+        __syncthreads();
+        for (int j = wid; j < n; j += 4) {
+            const int4 en = s_ent[j];
+            const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
+            const int nc = en.z & 255, nr = (en.z >> 8) & 255;
+            const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
+            const int jp = s_jp[j];
+            const C *tp = taps + s_off[j] + (int64_t)r0 * jp + c0;
+            const C y = s_y[j];
+            const float inv_nc = 1.0f / (float)nc;
+            const int ntap = nr * nc;
+            for (int k0 = 0; k0 < ntap; k0 += 64 * kU) {
+                C K[kU];
+                int li[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int k = k0 + 64 * u + lane;
+                    li[u] = -1;
+                    if (k < ntap) {
+                        // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
+                        int row = (int)(((float)k + 0.5f) * inv_nc);
+                        int col = k - row * nc;
+                        K[u] = tp[row * jp + col];
+                        li[u] = (ly0 + row) * kTile + lx0 + col;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (li[u] >= 0) {
+                        atomicAdd(&tre[li[u]], K[u].x * y.x + K[u].y * y.y);
+                        atomicAdd(&tim[li[u]], K[u].x * y.y - K[u].y * y.x);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t key = t.item_key[item];
+    C *dst;
+    int64_t ld;
+    if (t.item_sole[item]) {
+        // the tile's only item: store straight into the grid
+        const int tmask = (1 << t.tile_bits) - 1;
+        const int tx = key & tmask, ty = (key >> t.tile_bits) & tmask;
+        const int k = key >> (2 * t.tile_bits);
+        dst = grids + (int64_t)k * t.G * t.G + (int64_t)ty * kTile * t.G + (int64_t)tx * kTile;
+        ld = t.G;
+    } else {
+        // a shared tile: store this item's partial tile; k_reduce_tiles sums them
+        dst = (C *)t.partial + (int64_t)t.item_slot[item] * kTile * kTile;
+        ld = kTile;
+    }
+    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+        C v;
+        v.x = tre[i];
+        v.y = tim[i];
+        dst[(int64_t)(i / kTile) * ld + (i % kTile)] = v;
+    }
+}
+
+// Sum the partial tiles of each tile shared by several items, in item order
+// (deterministic), and store the result in the grid.
+template <bool kFP64>
+__global__ __launch_bounds__(256) void k_reduce_tiles(const int32_t *__restrict__ mt_first,
+                                                      typename Types<kFP64>::C *grids, TileArgs t) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    const int a = mt_first[blockIdx.x];
+    const uint32_t key = t.item_key[a];
+    int b = a + 1;
+    while (b < t.n_items && t.item_key[b] == key) ++b;
+    const int slot0 = t.item_slot[a];
+    const int tmask = (1 << t.tile_bits) - 1;
+    const int tx = key & tmask, ty = (key >> t.tile_bits) & tmask;
+    const int k = key >> (2 * t.tile_bits);
+    C *dst = grids + (int64_t)k * t.G * t.G + (int64_t)ty * kTile * t.G + (int64_t)tx * kTile;
+    const C *src = (const C *)t.partial + (int64_t)slot0 * kTile * kTile;
+    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+        R vr = 0, vi = 0;
+        for (int j = 0; j < b - a; ++j) {
+            C v = src[(int64_t)j * kTile * kTile + i];
+            vr += v.x;
+            vi += v.y;
+        }
+        C o;
+        o.x = vr;
+        o.y = vi;
+        dst[(int64_t)(i / kTile) * t.G + (i % kTile)] = o;
     }
 }
 
@@ -260,8 +433,9 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     if (e != hipSuccess) return e;
     ApplyArgs a = make_args(c);
     ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_degrid<kFP64>, dim3(blocks(a.m * 64, 256)), dim3(256), 0, s,
-                       (const C *)c->taps, (const C *)c->grids, (C *)vis, a);
+    unsigned nb = 8 * ((blocks(a.m * 64, 256) + 7) / 8);
+    hipLaunchKernelGGL(k_degrid<kFP64>, dim3(nb), dim3(256), 0, s, (const C *)c->taps,
+                       (const C *)c->grids, (C *)vis, a);
     stage_end(c, kStDegrid, ev, s);
     return hipGetLastError();
 }
@@ -277,9 +451,21 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     hipLaunchKernelGGL(k_zero<C>, dim3(blocks(ncell, 256)), dim3(256), 0, s, (C *)c->grids, ncell);
     stage_end(c, kStZero, ev, s);
     ApplyArgs a = make_args(c);
+    const Plan &pl = c->plan;
+    TileArgs ta{pl.ent,      pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole,
+                pl.item_slot, c->scratch_part, pl.jp, pl.tap_off, pl.n_items, pl.tile_bits, g.G};
     ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_grid<kFP64>, dim3(blocks(a.m * 64, 256)), dim3(256), 0, s,
-                       (const C *)c->taps, (const C *)vis, (C *)c->grids, a);
+    hipLaunchKernelGGL(k_prep_vis<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)vis,
+                       (C *)c->scratch_yw, a);
+    if (pl.n_items > 0) {
+        unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
+        hipLaunchKernelGGL(k_grid_tiles<kFP64>, dim3(nb), dim3(256), 0, s, (const C *)c->taps,
+                           (const C *)c->scratch_yw, (C *)c->grids, ta);
+    }
+    if (pl.n_mtiles > 0) {
+        hipLaunchKernelGGL(k_reduce_tiles<kFP64>, dim3(pl.n_mtiles), dim3(256), 0, s, pl.mt_first,
+                           (C *)c->grids, ta);
+    }
     stage_end(c, kStGrid, ev, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

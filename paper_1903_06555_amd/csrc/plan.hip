@@ -238,6 +238,117 @@ hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
 }
 
+// ------------------------------------------------ tile work lists ---------
+// A visibility's J_p x J_p footprint, starting at the wrapped first tap
+// (u0w, v0w), covers virtual tiles u0w / T .. (u0w + J_p - 1) / T (and the
+// same in v); virtual tile t lands on physical tile t mod (G / T), which
+// realises the circular convolution.  Each (visibility, tile) overlap is one
+// entry holding the overlapping sub-block of the visibility's taps.
+__global__ void k_entry_count(const int32_t *__restrict__ jp, const int32_t *__restrict__ u0w,
+                              const int32_t *__restrict__ v0w, int64_t m, int64_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > m) return;
+    if (i == m) {
+        cnt[i] = 0;
+        return;
+    }
+    int j = jp[i], u = u0w[i], v = v0w[i];
+    int64_t ntx = (u + j - 1) / kTile - u / kTile + 1;
+    int64_t nty = (v + j - 1) / kTile - v / kTile + 1;
+    cnt[i] = ntx * nty;
+}
+
+__global__ void k_entry_fill(const int32_t *__restrict__ jp, const int32_t *__restrict__ u0w,
+                             const int32_t *__restrict__ v0w, const int32_t *__restrict__ stack,
+                             const int64_t *__restrict__ eoff, int64_t m, int n_tiles,
+                             int tile_bits, int4 *ent, uint32_t *keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int j = jp[i], u = u0w[i], v = v0w[i];
+    const int tx0 = u / kTile, ty0 = v / kTile;
+    const int ntx = (u + j - 1) / kTile - tx0 + 1;
+    const int nty = (v + j - 1) / kTile - ty0 + 1;
+    const uint32_t sk = (uint32_t)stack[i] << (2 * tile_bits);
+    int64_t e = eoff[i];
+    for (int iy = 0; iy < nty; ++iy) {
+        int tvy = ty0 + iy;
+        int r0 = tvy * kTile - v;
+        r0 = r0 < 0 ? 0 : r0;
+        int r1 = (tvy + 1) * kTile - v;
+        r1 = r1 > j ? j : r1;
+        int ly0 = v + r0 - tvy * kTile;
+        uint32_t typ = (uint32_t)(tvy % n_tiles);
+        for (int ix = 0; ix < ntx; ++ix) {
+            int tvx = tx0 + ix;
+            int c0 = tvx * kTile - u;
+            c0 = c0 < 0 ? 0 : c0;
+            int c1 = (tvx + 1) * kTile - u;
+            c1 = c1 > j ? j : c1;
+            int lx0 = u + c0 - tvx * kTile;
+            uint32_t txp = (uint32_t)(tvx % n_tiles);
+            uint32_t key = sk | (typ << tile_bits) | txp;
+            ent[e] = make_int4((int)i, c0 | (r0 << 16),
+                               (c1 - c0) | ((r1 - r0) << 8) | (lx0 << 16) | (ly0 << 24), (int)key);
+            keys[e] = key;
+            ++e;
+        }
+    }
+}
+
+__global__ void k_entry_work(const uint32_t *__restrict__ keys_sorted,
+                             const int32_t *__restrict__ idx_sorted, const int4 *__restrict__ ent,
+                             int64_t E, int64_t *work, uint8_t *head) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= E) return;
+    int z = ent[idx_sorted[s]].z;
+    work[s] = (int64_t)(z & 255) * ((z >> 8) & 255);
+    head[s] = (s == 0 || keys_sorted[s] != keys_sorted[s - 1]) ? 1 : 0;
+}
+
+__global__ void k_seg_base_cand(const int64_t *__restrict__ incl, const int64_t *__restrict__ work,
+                                const uint8_t *__restrict__ head, int64_t E, int64_t *cand) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < E) cand[s] = head[s] ? incl[s] - work[s] : 0;
+}
+
+// An item starts where a tile starts or where the tap count since the tile
+// start crosses a multiple of kItemTaps.
+__global__ void k_item_head(const int64_t *__restrict__ incl, const int64_t *__restrict__ work,
+                            const int64_t *__restrict__ segbase, const uint8_t *__restrict__ head,
+                            int64_t E, uint8_t *ihead) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= E) return;
+    if (head[s]) {
+        ihead[s] = 1;
+        return;
+    }
+    int64_t c = (incl[s] - work[s] - segbase[s]) / kItemTaps;
+    int64_t cp = (incl[s - 1] - work[s - 1] - segbase[s - 1]) / kItemTaps;
+    ihead[s] = c != cp ? 1 : 0;
+}
+
+__global__ void k_item_info(const int32_t *__restrict__ item_start, int n_items, int64_t E,
+                            const uint32_t *__restrict__ keys_sorted,
+                            const uint8_t *__restrict__ head, uint32_t *item_key, uint8_t *sole,
+                            int32_t *item_start_out_last) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    int s = item_start[i];
+    int64_t next = (i + 1 < n_items) ? item_start[i + 1] : E;
+    item_key[i] = keys_sorted[s];
+    sole[i] = (head[s] && (next == E || head[next])) ? 1 : 0;
+    if (i == n_items - 1) *item_start_out_last = (int32_t)E;
+}
+
+__global__ void k_multi_flags(const uint32_t *__restrict__ item_key,
+                              const uint8_t *__restrict__ sole, int n, int *shared_item,
+                              uint8_t *tile_head) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    shared_item[i] = sole[i] ? 0 : 1;
+    tile_head[i] = (!sole[i] && (i == 0 || item_key[i] != item_key[i - 1])) ? 1 : 0;
+}
+
 }  // namespace
 
 hipError_t launch_fold(const double *uvw, const double *wts, int64_t m, int fold, Plan &pl,
@@ -289,26 +400,183 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K, doub
     return e;
 }
 
-static void free_sorted(Plan &pl) {
-    hipFree(pl.perm);
-    hipFree(pl.ux);
-    hipFree(pl.vx);
-    hipFree(pl.weff);
-    hipFree(pl.wt);
-    hipFree(pl.jp);
-    hipFree(pl.u0w);
-    hipFree(pl.v0w);
-    hipFree(pl.stack);
-    hipFree(pl.sflag);
-    hipFree(pl.tap_off);
-    hipFree(pl.border);
-    hipFree(pl.stats);
-    pl.stats = nullptr;
+void free_sorted_plan(Plan &pl) {
+    void *ptrs[] = {pl.perm,   pl.ux,      pl.vx,         pl.weff,     pl.wt,
+                    pl.jp,     pl.u0w,     pl.v0w,        pl.stack,    pl.sflag,
+                    pl.tap_off, pl.border, pl.stats,      pl.ent,      pl.ent_off,
+                    pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole};
+    for (void *q : ptrs) hipFree(q);
     pl.perm = nullptr;
     pl.ux = pl.vx = pl.weff = pl.wt = nullptr;
     pl.jp = pl.u0w = pl.v0w = pl.stack = pl.border = nullptr;
     pl.sflag = nullptr;
     pl.tap_off = nullptr;
+    pl.stats = nullptr;
+    pl.ent = nullptr;
+    pl.ent_off = nullptr;
+    pl.ent_sorted = pl.item_start = nullptr;
+    pl.item_key = nullptr;
+    pl.item_sole = nullptr;
+    pl.n_entries = 0;
+    pl.n_items = 0;
+    hipFree(pl.item_slot);
+    hipFree(pl.mt_first);
+    pl.item_slot = pl.mt_first = nullptr;
+    pl.n_multi = pl.n_mtiles = 0;
+}
+
+// Tile work lists of the sorted visibilities (see k_entry_fill).
+static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream_t s) {
+    const int64_t m = pl.m;
+    const int n_tiles = g.G / kTile;
+    int64_t *cnt = nullptr, *work = nullptr, *incl = nullptr, *cand = nullptr, *segbase = nullptr;
+    uint32_t *keys = nullptr, *keys_sorted = nullptr;
+    int32_t *iota = nullptr, *d_nsel = nullptr;
+    uint8_t *head = nullptr, *ihead = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        void *ptrs[] = {cnt, work, incl, cand, segbase, keys, keys_sorted, iota, d_nsel, head, ihead, tmp};
+        for (void *q : ptrs) hipFree(q);
+    };
+#define WSP_ESTEP(expr)        \
+    do {                       \
+        e = (expr);            \
+        if (e != hipSuccess) { \
+            cleanup();         \
+            return e;          \
+        }                      \
+    } while (0)
+    auto scratch = [&](size_t need) -> hipError_t {
+        if (need <= tmp_bytes && tmp) return hipSuccess;
+        hipFree(tmp);
+        tmp = nullptr;
+        tmp_bytes = need;
+        return hipMalloc(&tmp, need ? need : 1);
+    };
+    size_t need = 0;
+
+    WSP_ESTEP(dalloc(&cnt, m + 1));
+    WSP_ESTEP(dalloc(&pl.ent_off, m + 1));
+    hipLaunchKernelGGL(k_entry_count, dim3(grid1d(m + 1, 256)), dim3(256), 0, s, pl.jp, pl.u0w,
+                       pl.v0w, m, cnt);
+    WSP_ESTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, need, cnt, pl.ent_off, (int)(m + 1), s));
+    WSP_ESTEP(scratch(need));
+    WSP_ESTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need, cnt, pl.ent_off, (int)(m + 1), s));
+    int64_t E = 0;
+    WSP_ESTEP(hipMemcpyAsync(&E, pl.ent_off + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    WSP_ESTEP(hipStreamSynchronize(s));
+    if (E >= 0x7FFFFFF0LL) {
+        cleanup();
+        return hipErrorInvalidValue;
+    }
+    pl.n_entries = E;
+
+    WSP_ESTEP(dalloc(&pl.ent, E));
+    WSP_ESTEP(dalloc(&keys, E));
+    WSP_ESTEP(dalloc(&keys_sorted, E));
+    WSP_ESTEP(dalloc(&iota, E));
+    WSP_ESTEP(dalloc(&pl.ent_sorted, E));
+    hipLaunchKernelGGL(k_entry_fill, dim3(grid1d(m, 256)), dim3(256), 0, s, pl.jp, pl.u0w, pl.v0w,
+                       pl.stack, pl.ent_off, m, n_tiles, tile_bits, pl.ent, keys);
+    hipLaunchKernelGGL(k_iota, dim3(grid1d(E, 256)), dim3(256), 0, s, iota, E);
+    WSP_ESTEP(hipGetLastError());
+    int stack_bits = 0;
+    while ((1 << stack_bits) < g.n_stacks) ++stack_bits;
+    int key_bits = 2 * tile_bits + stack_bits;
+    key_bits = key_bits > 0 ? key_bits : 1;
+    need = 0;
+    WSP_ESTEP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys_sorted, iota,
+                                                 pl.ent_sorted, (int)E, 0, key_bits, s));
+    WSP_ESTEP(scratch(need));
+    WSP_ESTEP(hipcub::DeviceRadixSort::SortPairs(tmp, need, keys, keys_sorted, iota, pl.ent_sorted,
+                                                 (int)E, 0, key_bits, s));
+
+    // work items: cut each tile's entries every kItemTaps taps
+    WSP_ESTEP(dalloc(&work, E));
+    WSP_ESTEP(dalloc(&incl, E));
+    WSP_ESTEP(dalloc(&cand, E));
+    WSP_ESTEP(dalloc(&segbase, E));
+    WSP_ESTEP(dalloc(&head, E));
+    WSP_ESTEP(dalloc(&ihead, E));
+    hipLaunchKernelGGL(k_entry_work, dim3(grid1d(E, 256)), dim3(256), 0, s, keys_sorted,
+                       pl.ent_sorted, pl.ent, E, work, head);
+    need = 0;
+    WSP_ESTEP(hipcub::DeviceScan::InclusiveSum(nullptr, need, work, incl, (int)E, s));
+    WSP_ESTEP(scratch(need));
+    WSP_ESTEP(hipcub::DeviceScan::InclusiveSum(tmp, need, work, incl, (int)E, s));
+    hipLaunchKernelGGL(k_seg_base_cand, dim3(grid1d(E, 256)), dim3(256), 0, s, incl, work, head,
+                       E, cand);
+    need = 0;
+    WSP_ESTEP(hipcub::DeviceScan::InclusiveScan(nullptr, need, cand, segbase, hipcub::Max(), (int)E, s));
+    WSP_ESTEP(scratch(need));
+    WSP_ESTEP(hipcub::DeviceScan::InclusiveScan(tmp, need, cand, segbase, hipcub::Max(), (int)E, s));
+    hipLaunchKernelGGL(k_item_head, dim3(grid1d(E, 256)), dim3(256), 0, s, incl, work, segbase,
+                       head, E, ihead);
+    WSP_ESTEP(hipGetLastError());
+    // item starts = indices s with ihead[s] = 1 (at most E items)
+    WSP_ESTEP(dalloc(&pl.item_start, E + 1));
+    WSP_ESTEP(dalloc(&d_nsel, 1));
+    hipcub::CountingInputIterator<int32_t> counting(0);
+    need = 0;
+    WSP_ESTEP(hipcub::DeviceSelect::Flagged(nullptr, need, counting, ihead, pl.item_start, d_nsel,
+                                            (int)E, s));
+    WSP_ESTEP(scratch(need));
+    WSP_ESTEP(hipcub::DeviceSelect::Flagged(tmp, need, counting, ihead, pl.item_start, d_nsel,
+                                            (int)E, s));
+    int nsel = 0;
+    WSP_ESTEP(hipMemcpyAsync(&nsel, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s));
+    WSP_ESTEP(hipStreamSynchronize(s));
+    pl.n_items = nsel;
+    WSP_ESTEP(dalloc(&pl.item_key, nsel));
+    WSP_ESTEP(dalloc(&pl.item_sole, nsel));
+    hipLaunchKernelGGL(k_item_info, dim3(grid1d(nsel, 256)), dim3(256), 0, s, pl.item_start, nsel,
+                       E, keys_sorted, head, pl.item_key, pl.item_sole, pl.item_start + nsel);
+    WSP_ESTEP(hipGetLastError());
+    // items of tiles split over several items write partial tiles to slots
+    // (in item order); the tiles' first items index the reduction
+    {
+        int *shared_item = nullptr;
+        WSP_ESTEP(dalloc(&shared_item, nsel + 1));
+        WSP_ESTEP(dalloc(&pl.item_slot, nsel + 1));
+        WSP_ESTEP(dalloc(&pl.mt_first, nsel + 1));
+        uint8_t *tile_head = ihead;  // reuse (E >= nsel)
+        hipLaunchKernelGGL(k_multi_flags, dim3(grid1d(nsel, 256)), dim3(256), 0, s, pl.item_key,
+                           pl.item_sole, nsel, shared_item, tile_head);
+        e = hipMemsetAsync(shared_item + nsel, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            need = 0;
+            e = hipcub::DeviceScan::ExclusiveSum(nullptr, need, shared_item, pl.item_slot, nsel + 1, s);
+        }
+        if (e == hipSuccess) e = scratch(need);
+        if (e == hipSuccess)
+            e = hipcub::DeviceScan::ExclusiveSum(tmp, need, shared_item, pl.item_slot, nsel + 1, s);
+        if (e == hipSuccess) {
+            need = 0;
+            e = hipcub::DeviceSelect::Flagged(nullptr, need, counting, tile_head, pl.mt_first, d_nsel,
+                                              nsel, s);
+        }
+        if (e == hipSuccess) e = scratch(need);
+        if (e == hipSuccess)
+            e = hipcub::DeviceSelect::Flagged(tmp, need, counting, tile_head, pl.mt_first, d_nsel,
+                                              nsel, s);
+        int nmt = 0, nmulti = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&nmt, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&nmulti, pl.item_slot + nsel, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pl.mt_first + nmt, &nsel, sizeof(int), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFree(shared_item);
+        WSP_ESTEP(e);
+        pl.n_mtiles = nmt;
+        pl.n_multi = nmulti;
+    }
+    cleanup();
+    return hipSuccess;
+#undef WSP_ESTEP
 }
 
 hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err) {
@@ -316,7 +584,7 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     const Geom &g = c->g;
     const int64_t m = pl.m;
     *support_err = 0;
-    free_sorted(pl);
+    free_sorted_plan(pl);
 
     int tiles = g.G / kTile;
     int tile_bits = 0;
@@ -448,8 +716,9 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     WSP_STEP(hipStreamSynchronize(s));
     pl.total_taps = total;
     pl.max_jp = mx;
+    pl.tile_bits = tile_bits;
     cleanup();
-    return hipSuccess;
+    return make_entries(pl, g, tile_bits, s);
 #undef WSP_STEP
 }
 

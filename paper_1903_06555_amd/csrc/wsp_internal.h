@@ -16,6 +16,7 @@ constexpr int kWave = 64;
 constexpr int kTile = 64;          // grid tile side (cells) used for sort keys
 constexpr int kMaxPanels = 1024;   // quadrature panels per visibility (LDS bound)
 constexpr int kProbes = 8;         // probe distances used by the panel error estimate
+constexpr int64_t kItemTaps = 1 << 19; // taps per tile work item (upper bound before the last entry)
 
 // Geometry of one operator, all derived once on the host (FP64).
 struct Geom {
@@ -61,6 +62,21 @@ struct Plan {
     unsigned long long *stats = nullptr;  // [0] panels, [1] capped visibilities
     int64_t total_taps = 0;
     int32_t max_jp = 0;
+    // tile work lists: one entry per (visibility, grid tile) overlap, sorted by
+    // (stack, tile) and cut into work items of bounded tap count
+    int64_t n_entries = 0;
+    int n_items = 0;
+    int4 *ent = nullptr;          // [n_entries] {vis, c0 | r0 << 16, nc | nr << 8 | lx0 << 16 | ly0 << 24, key}
+    int64_t *ent_off = nullptr;   // [m + 1] first entry of each sorted visibility
+    int32_t *ent_sorted = nullptr;// [n_entries] entry indices in (stack, tile) order
+    int32_t *item_start = nullptr;// [n_items + 1] ranges of ent_sorted
+    uint32_t *item_key = nullptr; // [n_items] (stack, tile) key of each item
+    uint8_t *item_sole = nullptr; // [n_items] 1 if the item is its tile's only item
+    int32_t *item_slot = nullptr; // [n_items] partial-tile slot of a shared tile's item
+    int n_multi = 0;              // items whose tile is split over several items
+    int n_mtiles = 0;             // tiles split over several items
+    int32_t *mt_first = nullptr;  // [n_mtiles + 1] first item of each split tile (+ n_items)
+    int tile_bits = 0;
 };
 
 // Stages timed with HIP events when timing is enabled (wsp_set_timing).
@@ -95,6 +111,8 @@ struct wsp_ctx {
     size_t grid_bytes = 0;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    void *scratch_yw = nullptr;     // weighted adjoint input, sorted order (inside scratch)
+    void *scratch_part = nullptr;   // partial tiles of shared grid tiles (inside scratch)
     bool bound = false;
     bool built = false;
     int64_t built_upto = 0;         // visibilities built so far, in build order
@@ -114,6 +132,7 @@ hipError_t minmax_w(const Plan &pl, double *wmin, double *wmax, hipStream_t s);
 hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K,
                             double *h_new_centres, hipStream_t s);
 hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err);
+void free_sorted_plan(Plan &pl);
 
 // build.hip
 hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s);
