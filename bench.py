@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--m-vis", type=int, default=None, help="override visibility count (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6)
+    ap.add_argument("--mode", default="operator", choices=["operator", "copy"],
+                    help="operator: the metric; copy: a plain 2 GiB device copy used to "
+                         "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
     return ap.parse_args()
 
 
@@ -101,11 +104,31 @@ def cpu_baseline(wl, uvw, x, y, sample_n: int, total_taps: int, jp_all):
     }
 
 
+def copy_calibration(steps: int):
+    """A plain device-to-device copy of known size (counter calibration)."""
+    import torch
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": nbytes,
+                      "bytes_written_per_launch": nbytes, "launches": steps,
+                      "GB_s": 2 * nbytes / dt / 1e9}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.mode == "copy":
+        copy_calibration(args.steps)
+        return
 
     import torch
 

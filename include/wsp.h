@@ -121,9 +121,9 @@ wsp_status wsp_get_support(const wsp_ctx *ctx, int32_t *jp, uint8_t *folded);
 
 /* Exact byte sizes of the caller-owned buffers after wsp_set_uvw:
  * kernel taps (sum_p J_p^2 complex values), the K Fourier grids (K G^2
- * complex values) and scratch (FFT work area, M complex values, and one
- * 64 x 64 complex partial tile per work item of a grid tile that is split
- * over several items).
+ * complex values) and scratch (FFT work area, M complex values, one complex
+ * partial sum per (visibility, grid tile) overlap, and one 64 x 64 complex
+ * partial tile per work item of a grid tile split over several items).
  * Errors: WSP_ESTATE. */
 wsp_status wsp_footprint(const wsp_ctx *ctx, size_t *kernel_bytes,
                          size_t *grid_bytes, size_t *scratch_bytes);

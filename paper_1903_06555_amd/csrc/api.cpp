@@ -365,6 +365,7 @@ wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_by
     if (grid_bytes) *grid_bytes = (size_t)c->g.G * c->g.G * c->g.n_stacks * cb;
     if (scratch_bytes)
         *scratch_bytes = align256(c->fft_work) + align256((size_t)c->plan.m * cb) +
+                         align256((size_t)c->plan.n_entries * cb) +
                          (size_t)c->plan.n_multi * kTile * kTile * cb;
     return WSP_OK;
 }
@@ -384,7 +385,9 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
     if (c->fft_work > 0 && hipfftSetWorkArea(c->fft, scratch) != HIPFFT_SUCCESS)
         return fail(WSP_EHIP, "hipfftSetWorkArea failed");
     c->scratch_yw = (char *)scratch + align256(c->fft_work);
-    c->scratch_part = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
+    c->scratch_dpart = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
+    c->scratch_part =
+        (char *)c->scratch_dpart + align256((size_t)c->plan.n_entries * cplx_bytes(c));
     c->taps = kernels;
     c->taps_bytes = kernel_bytes;
     c->grids = grids;

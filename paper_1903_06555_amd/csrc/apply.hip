@@ -1,9 +1,12 @@
 // Operator application: y = Phi x (degrid) and x = Re Phi^dagger y (grid),
 // Eqs. (2)-(7).  Per stack k:
 //   degrid: S~_k and Z (k_taper_pad), F (hipFFT, batched over stacks),
-//           GC_k and W_k (k_degrid);
-//   grid:   W_k, GC_k^dagger (k_grid), F^dagger (hipFFT), Z^dagger, S~_k^dagger,
-//           Re and the sum over stacks (k_crop_untaper).
+//           GC_k and W_k (k_degrid_tiles, k_degrid_reduce);
+//   grid:   W_k (k_prep_vis), GC_k^dagger (k_grid_tiles, k_reduce_tiles),
+//           F^dagger (hipFFT), Z^dagger, S~_k^dagger, Re and the sum over
+//           stacks (k_crop_untaper).
+// Both sparse steps work on the tile work lists of the plan: each work item
+// is a run of (visibility, 64 x 64 grid tile) entries of one tile.
 #include "wsp_devmath.h"
 
 namespace wsp {
@@ -134,85 +137,10 @@ struct ApplyArgs {
     Geom g;
 };
 
-__device__ __forceinline__ int wrap_index(int x, int G) {
-    while (x >= G) x -= G;
-    return x;
-}
-
 template <typename R>
 __device__ __forceinline__ R wave_sum_r(R x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
-}
-
-// GC_k, W_k: one wavefront per visibility, lanes over taps.  Waves are
-// mapped XCD-aware: each of the 8 XCDs takes a contiguous run of the sorted
-// visibilities, so the grid region it gathers from stays in its own L2.  Tap
-// coordinates advance incrementally (no division in the loop).
-template <bool kFP64>
-__global__ __launch_bounds__(256) void k_degrid(const typename Types<kFP64>::C *__restrict__ taps,
-                                                const typename Types<kFP64>::C *__restrict__ grids,
-                                                typename Types<kFP64>::C *vis, ApplyArgs a) {
-    using R = typename Types<kFP64>::R;
-    using C = typename Types<kFP64>::C;
-    constexpr int kU = 4;  // taps per lane in flight
-    const int lane = threadIdx.x & 63;
-    const int nblk = gridDim.x;
-    const int per = nblk / 8;  // gridDim.x is a multiple of 8
-    const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    // wave-uniform visibility index (metadata through the scalar cache)
-    const int64_t p = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
-    if (p >= a.m) return;
-    const int G = a.g.G;
-    const int jp = a.jp[p];
-    const int u0 = a.u0w[p], v0 = a.v0w[p];
-    const C *tp = taps + a.tap_off[p];
-    const C *gk = grids + (int64_t)a.stack[p] * G * G;
-    const int ntap = jp * jp;
-    // lane's first tap (t = lane) and the per-step advance of 64 taps
-    int row = lane / jp, col = lane - (lane / jp) * jp;
-    const int drow = 64 / jp, dcol = 64 - (64 / jp) * jp;
-    int V = v0 + row;
-    while (V >= G) V -= G;
-    R ar = 0, ai = 0;
-    for (int t0 = 0; t0 < ntap; t0 += 64 * kU) {
-        C K[kU], z[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int t = t0 + 64 * u + lane;
-            int U = u0 + col;
-            while (U >= G) U -= G;
-            if (t < ntap) {
-                K[u] = tp[t];
-                z[u] = gk[(int64_t)V * G + U];
-            } else {
-                K[u].x = K[u].y = 0;
-                z[u].x = z[u].y = 0;
-            }
-            col += dcol;
-            int dr = drow;
-            if (col >= jp) {
-                col -= jp;
-                ++dr;
-            }
-            V += dr;
-            while (V >= G) V -= G;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            ar += K[u].x * z[u].x - K[u].y * z[u].y;
-            ai += K[u].x * z[u].y + K[u].y * z[u].x;
-        }
-    }
-    ar = wave_sum_r(ar);
-    ai = wave_sum_r(ai);
-    if (lane == 0) {
-        R w = (R)a.wt[p];
-        C y;
-        y.x = ar * w;
-        y.y = (a.sflag[p] ? -ai : ai) * w;  // Eq. (8): folded visibilities are conjugated
-        vis[a.perm[p]] = y;
-    }
 }
 
 // W_k and Eq. (8) on the adjoint's input: yw[p] = W_p (conj) y[perm[p]] in
@@ -255,42 +183,55 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     return (b % nx) * per + b / nx;
 }
 
-// GC_k^dagger: one block per work item (a run of entries of one grid tile).
-// The tile is privatised in LDS; the four wavefronts take entries in turn,
-// lanes walk the entry's tap sub-block and add conj(K) yw with LDS atomics;
-// the tile is then stored (its only item) or added atomically to the grid.
+// First cell of a (stack, tile) key in the grids.
+template <typename C>
+__device__ __forceinline__ C *tile_origin(C *grids, uint32_t key, const TileArgs &t) {
+    const int tmask = (1 << t.tile_bits) - 1;
+    const int tx = key & tmask, ty = (key >> t.tile_bits) & tmask;
+    const int k = key >> (2 * t.tile_bits);
+    return grids + (int64_t)k * t.G * t.G + (int64_t)ty * kTile * t.G + (int64_t)tx * kTile;
+}
+
+constexpr int kChunk = 256;           // entries whose metadata is staged in LDS at a time
+constexpr int kBand = kTile / 4;      // tile rows owned by each of the 4 wavefronts
+
+// GC_k, W_k (degrid), one block per work item: the item's 64 x 64 grid tile
+// is staged in LDS; the four wavefronts take entries in turn, lanes walk the
+// entry's tap sub-block, multiply by the staged grid values and reduce; each
+// entry's partial sum goes to dpart[entry] (entries are stored grouped by
+// visibility), summed per visibility by k_degrid_reduce.
 template <bool kFP64>
-__global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
-                                                    const typename Types<kFP64>::C *__restrict__ yw,
-                                                    typename Types<kFP64>::C *grids, TileArgs t) {
+__global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+                                                      const typename Types<kFP64>::C *__restrict__ grids,
+                                                      typename Types<kFP64>::C *dpart, TileArgs t) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    constexpr int kChunk = 256;  // entries whose metadata is staged in LDS at a time
-    constexpr int kU = 8;        // taps per lane in flight
-    __shared__ R tre[kTile * kTile];
-    __shared__ R tim[kTile * kTile];
+    constexpr int kU = 4;
+    __shared__ C tile[kTile * kTile];
     __shared__ int4 s_ent[kChunk];
+    __shared__ int s_idx[kChunk];
     __shared__ int64_t s_off[kChunk];
     __shared__ int s_jp[kChunk];
-    __shared__ C s_y[kChunk];
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
-        tre[i] = 0;
-        tim[i] = 0;
+    {
+        const C *src = tile_origin(grids, t.item_key[item], t);
+        for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x)
+            tile[i] = src[(int64_t)(i / kTile) * t.G + (i % kTile)];
     }
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
     for (int base = s_beg; base < s_end; base += kChunk) {
         const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
-        __syncthreads();  // LDS tile cleared / previous chunk consumed
+        __syncthreads();  // tile staged / previous chunk consumed
         if ((int)threadIdx.x < n) {
-            const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
+            const int e = t.ent_sorted[base + threadIdx.x];
+            const int4 en = t.ent[e];
             s_ent[threadIdx.x] = en;
+            s_idx[threadIdx.x] = e;
             s_off[threadIdx.x] = t.tap_off[en.x];
             s_jp[threadIdx.x] = t.jp[en.x];
-            s_y[threadIdx.x] = yw[en.x];
         }
         __syncthreads();
         for (int j = wid; j < n; j += 4) {
@@ -300,55 +241,143 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
             const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
             const int jp = s_jp[j];
             const C *tp = taps + s_off[j] + (int64_t)r0 * jp + c0;
-            const C y = s_y[j];
             const float inv_nc = 1.0f / (float)nc;
             const int ntap = nr * nc;
+            R ar = 0, ai = 0;
             for (int k0 = 0; k0 < ntap; k0 += 64 * kU) {
                 C K[kU];
                 int li[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     const int k = k0 + 64 * u + lane;
-                    li[u] = -1;
-                    if (k < ntap) {
-                        // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
-                        int row = (int)(((float)k + 0.5f) * inv_nc);
-                        int col = k - row * nc;
+                    // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
+                    const int row = (int)(((float)k + 0.5f) * inv_nc);
+                    const int col = k - row * nc;
+                    const bool ok = k < ntap;
+                    li[u] = ok ? (ly0 + row) * kTile + lx0 + col : 0;
+                    if (ok) {
                         K[u] = tp[row * jp + col];
-                        li[u] = (ly0 + row) * kTile + lx0 + col;
+                    } else {
+                        K[u].x = 0;
+                        K[u].y = 0;
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    if (li[u] >= 0) {
-                        atomicAdd(&tre[li[u]], K[u].x * y.x + K[u].y * y.y);
-                        atomicAdd(&tim[li[u]], K[u].x * y.y - K[u].y * y.x);
-                    }
+                    const C z = tile[li[u]];
+                    ar += K[u].x * z.x - K[u].y * z.y;
+                    ai += K[u].x * z.y + K[u].y * z.x;
+                }
+            }
+            ar = wave_sum_r(ar);
+            ai = wave_sum_r(ai);
+            if (lane == 0) {
+                C o;
+                o.x = ar;
+                o.y = ai;
+                dpart[s_idx[j]] = o;
+            }
+        }
+    }
+}
+
+// y[perm[p]] = W_p (conj) sum of visibility p's entry partials, in entry order.
+template <bool kFP64>
+__global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpart,
+                                const int64_t *__restrict__ ent_off,
+                                typename Types<kFP64>::C *vis, ApplyArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.m) return;
+    R ar = 0, ai = 0;
+    for (int64_t e = ent_off[p]; e < ent_off[p + 1]; ++e) {
+        C v = dpart[e];
+        ar += v.x;
+        ai += v.y;
+    }
+    R w = (R)a.wt[p];
+    C y;
+    y.x = ar * w;
+    y.y = (a.sflag[p] ? -ai : ai) * w;  // Eq. (8): folded visibilities are conjugated
+    vis[a.perm[p]] = y;
+}
+
+// GC_k^dagger (grid), one block per work item, no atomics: each of the four
+// wavefronts owns a band of 16 tile rows and keeps them in registers (lane =
+// tile column); every wavefront walks all entries of the item and adds
+// conj(K) yw for the entry rows inside its band.  The tile is then stored
+// into the grid (the tile's only item) or into a partial-tile slot that
+// k_reduce_tiles sums in item order.
+template <bool kFP64>
+__global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+                                                    const typename Types<kFP64>::C *__restrict__ yw,
+                                                    typename Types<kFP64>::C *grids, TileArgs t) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    __shared__ int4 s_ent[kChunk];
+    __shared__ int64_t s_off[kChunk];
+    __shared__ int s_jp[kChunk];
+    __shared__ C s_y[kChunk];
+    const int item = xcd_item(blockIdx.x, t.n_items);
+    if (item >= t.n_items) return;  // uniform over the block
+    const int lane = threadIdx.x & 63;
+    const int band0 = (threadIdx.x >> 6) * kBand;
+    R accr[kBand], acci[kBand];
+#pragma unroll
+    for (int r = 0; r < kBand; ++r) accr[r] = acci[r] = 0;
+    const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
+    for (int base = s_beg; base < s_end; base += kChunk) {
+        const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
+        __syncthreads();  // previous chunk consumed
+        if ((int)threadIdx.x < n) {
+            const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
+            s_ent[threadIdx.x] = en;
+            s_off[threadIdx.x] = t.tap_off[en.x];
+            s_jp[threadIdx.x] = t.jp[en.x];
+            s_y[threadIdx.x] = yw[en.x];
+        }
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            const int4 en = s_ent[j];
+            const int nr = (en.z >> 8) & 255, ly0 = (en.z >> 24) & 255;
+            const int lo = ly0 > band0 ? ly0 : band0;
+            const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
+            if (lo >= hi) continue;  // no entry row in this band (uniform)
+            const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
+            const int nc = en.z & 255, lx0 = (en.z >> 16) & 255;
+            const int jp = s_jp[j];
+            const bool colok = lane >= lx0 && lane < lx0 + nc;
+            // tap of tile cell (row, lane): entry row r0 + row - ly0, column c0 + lane - lx0
+            const C *tp = taps + s_off[j] + (int64_t)(r0 - ly0) * jp + (c0 - lx0) + lane;
+            const C y = s_y[j];
+#pragma unroll
+            for (int r = 0; r < kBand; ++r) {
+                const int row = band0 + r;
+                if (row >= lo && row < hi && colok) {
+                    const C K = tp[(int64_t)row * jp];
+                    accr[r] += K.x * y.x + K.y * y.y;
+                    acci[r] += K.x * y.y - K.y * y.x;
                 }
             }
         }
     }
-    __syncthreads();
     const uint32_t key = t.item_key[item];
     C *dst;
     int64_t ld;
     if (t.item_sole[item]) {
-        // the tile's only item: store straight into the grid
-        const int tmask = (1 << t.tile_bits) - 1;
-        const int tx = key & tmask, ty = (key >> t.tile_bits) & tmask;
-        const int k = key >> (2 * t.tile_bits);
-        dst = grids + (int64_t)k * t.G * t.G + (int64_t)ty * kTile * t.G + (int64_t)tx * kTile;
+        dst = tile_origin(grids, key, t);
         ld = t.G;
     } else {
-        // a shared tile: store this item's partial tile; k_reduce_tiles sums them
         dst = (C *)t.partial + (int64_t)t.item_slot[item] * kTile * kTile;
         ld = kTile;
     }
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < kBand; ++r) {
         C v;
-        v.x = tre[i];
-        v.y = tim[i];
-        dst[(int64_t)(i / kTile) * ld + (i % kTile)] = v;
+        v.x = accr[r];
+        v.y = acci[r];
+        dst[(int64_t)(band0 + r) * ld + lane] = v;
     }
 }
 
@@ -432,10 +461,17 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     stage_end(c, kStFftForward, ev, s);
     if (e != hipSuccess) return e;
     ApplyArgs a = make_args(c);
+    const Plan &pl = c->plan;
+    TileArgs ta{pl.ent,      pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole,
+                pl.item_slot, c->scratch_part, pl.jp, pl.tap_off, pl.n_items, pl.tile_bits, g.G};
     ev = stage_begin(c, s);
-    unsigned nb = 8 * ((blocks(a.m * 64, 256) + 7) / 8);
-    hipLaunchKernelGGL(k_degrid<kFP64>, dim3(nb), dim3(256), 0, s, (const C *)c->taps,
-                       (const C *)c->grids, (C *)vis, a);
+    if (pl.n_items > 0) {
+        unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
+        hipLaunchKernelGGL(k_degrid_tiles<kFP64>, dim3(nb), dim3(256), 0, s, (const C *)c->taps,
+                           (const C *)c->grids, (C *)c->scratch_dpart, ta);
+    }
+    hipLaunchKernelGGL(k_degrid_reduce<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s,
+                       (const C *)c->scratch_dpart, pl.ent_off, (C *)vis, a);
     stage_end(c, kStDegrid, ev, s);
     return hipGetLastError();
 }

@@ -54,6 +54,16 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Broadcast lane n's value to the wavefront (n wave-uniform).
+__device__ __forceinline__ float readlane_f32(float x, int n) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), n));
+}
+__device__ __forceinline__ double readlane_f64(double x, int n) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), n);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), n);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
@@ -289,7 +299,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
     const int64_t cbase = (int64_t)(unit - unit_off[i]) * chunk;
 
     double q[kTapsPerLane];
-    float qf[kTapsPerLane];
+    float qf[kTapsPerLane], qinv[kTapsPerLane], qrs[kTapsPerLane];
     double accr[kTapsPerLane], acci[kTapsPerLane];
 #pragma unroll
     for (int k = 0; k < kTapsPerLane; ++k) {
@@ -299,6 +309,9 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         double du = ux - (double)col, dv = vx - (double)row;
         q[k] = (t < ntap) ? sqrt(du * du + dv * dv) : 0.0;
         qf[k] = (float)(kTwoPi * q[k]);
+        // per-tap factors of 8 / x and sqrt(2 / (pi x)) (unused when q = 0)
+        qinv[k] = q[k] > 0.0 ? (float)(1.0 / q[k]) : 0.0f;
+        qrs[k] = q[k] > 0.0 ? (float)(1.0 / sqrt(q[k])) : 0.0f;
         accr[k] = acci[k] = 0.0;
     }
     for (int pg = 0; pg < P; pg += kPanelGroup) {
@@ -323,8 +336,8 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
 #pragma unroll
             for (int k = 0; k < kTapsPerLane; ++k) pr[k] = pi_[k] = 0.0;
             for (int n = 0; n < nn; ++n) {
-                double rn = __shfl(nr, n, kWave);
-                double are = __shfl(nre, n, kWave), aim = __shfl(nim, n, kWave);
+                const double rn = readlane_f64(nr, n);
+                const double are = readlane_f64(nre, n), aim = readlane_f64(nim, n);
 #pragma unroll
                 for (int k = 0; k < kTapsPerLane; ++k) {
                     if (cbase + (int64_t)k * kWave < ntap) {
@@ -340,20 +353,25 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
                 acci[k] += pi_[k];
             }
         } else {
-            float nref = (float)nre, nimf = (float)nim;
+            // per-node factors, broadcast with readlane (no LDS round trip)
+            const float nref = (float)nre, nimf = (float)nim;
+            const float rinv = nr > 0.0 ? (float)(1.2732395447351627 / nr) : 0.0f;  // (4/pi) / r
+            const float rrs = nr > 0.0 ? (float)(0.3183098861837907 / sqrt(nr)) : 0.0f;  // 1 / (pi sqrt r)
+            const float nrf = (float)nr;
             // FP32 partial sums over one panel (15 nodes), accumulated in FP64
             for (int pb = 0; pb < nn; pb += WSP_GK_N) {
                 float pr[kTapsPerLane], pi_[kTapsPerLane];
 #pragma unroll
                 for (int k = 0; k < kTapsPerLane; ++k) pr[k] = pi_[k] = 0.0f;
                 for (int n = pb; n < pb + WSP_GK_N; ++n) {
-                    double rn = __shfl(nr, n, kWave);
-                    float are = __shfl(nref, n, kWave), aim = __shfl(nimf, n, kWave);
-                    float rnf = (float)rn;
+                    const double rn = readlane_f64(nr, n);
+                    const float are = readlane_f32(nref, n), aim = readlane_f32(nimf, n);
+                    const float ri = readlane_f32(rinv, n), rr = readlane_f32(rrs, n);
+                    const float rnf = readlane_f32(nrf, n);
 #pragma unroll
                     for (int k = 0; k < kTapsPerLane; ++k) {
                         if (cbase + (int64_t)k * kWave < ntap) {
-                            float J = j0_fp64phase(rn, q[k], rnf * qf[k]);
+                            float J = j0_fp64phase(rn, q[k], rnf * qf[k], ri * qinv[k], rr * qrs[k]);
                             pr[k] = fmaf(are, J, pr[k]);
                             pi_[k] = fmaf(aim, J, pi_[k]);
                         }

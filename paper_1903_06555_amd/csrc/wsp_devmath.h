@@ -58,13 +58,17 @@ __device__ __forceinline__ void sincos_rev(float f, float *sn, float *cs) {
     *cs = ((q + 1) & 2) ? -c1 : c1;
 }
 
-// J0(2 pi r q) for the FP32 path.  x < 8: Chebyshev series in FP64 (no
-// transcendental, same issue rate as FP32 on CDNA without packed math);
-// x >= 8: Hankel form in FP32 with the Bessel phase reduced in FP64.
-// xf = 2 pi r q in FP32 (used where relative precision suffices).
-__device__ __forceinline__ float j0_fp64phase(double r, double q, float xf) {
+// J0(2 pi r q) for the FP32 path.
+//   x < 8:  Chebyshev series in FP64 (no transcendental; an FP64 FMA issues
+//           at the FP32 rate on CDNA without packed math);
+//   x >= 8: Hankel form sqrt(2/(pi x)) (P0 cos(x - pi/4) - Q0 sin(x - pi/4))
+//           in FP32, with the phase (x - pi/4) / (2 pi) = r q - 1/8
+//           revolutions reduced in FP64.
+// The caller passes xf = 2 pi r q, inv = 8 / x and amp = sqrt(2 / (pi x)) in
+// FP32, formed from per-node and per-tap factors so that no division or
+// square root is needed per evaluation.
+__device__ __forceinline__ float j0_fp64phase(double r, double q, float xf, float inv, float amp) {
     if (xf < 8.0f) {
-        // Chebyshev series in u = 2 (x/8)^2 - 1, Clenshaw recurrence
         double x = kTwoPi * (r * q);
         double u = fma(x * x, 1.0 / 32.0, -1.0);
         double u2 = 2.0 * u;
@@ -77,12 +81,13 @@ __device__ __forceinline__ float j0_fp64phase(double r, double q, float xf) {
         }
         return (float)fma(u, b1, wsp_j0s_c[0] - b2);
     }
-    // Hankel form: sqrt(2/(pi x)) (P0 cos(x - pi/4) - Q0 sin(x - pi/4));
-    // (x - pi/4) / (2 pi) = r q - 1/8 revolutions, reduced in FP64.
-    float f = (float)reduce_rev(fma(r, q, -0.125));
+    // round-to-nearest by the 1.5 * 2^52 shift (|r q| < 2^51)
+    const double kShift = 6755399441055744.0;
+    double s = fma(r, q, -0.125);
+    double k = (s + kShift) - kShift;
+    float f = (float)(s - k);
     float sn, cs;
     sincos_rev(f, &sn, &cs);
-    float inv = 8.0f / xf;
     float t = inv * inv;
     float P = wsp_j0l_p[WSP_J0L_N - 1];
     float Q = wsp_j0l_q[WSP_J0L_N - 1];
@@ -92,7 +97,6 @@ __device__ __forceinline__ float j0_fp64phase(double r, double q, float xf) {
         Q = fmaf(Q, t, wsp_j0l_q[i]);
     }
     Q *= inv;
-    float amp = 0.79788456080286535588f * rsqrtf(xf);  // sqrt(2/pi) / sqrt(x)
     return amp * (P * cs - Q * sn);
 }
 

@@ -113,6 +113,7 @@ struct wsp_ctx {
     size_t scratch_bytes = 0;
     void *scratch_yw = nullptr;     // weighted adjoint input, sorted order (inside scratch)
     void *scratch_part = nullptr;   // partial tiles of shared grid tiles (inside scratch)
+    void *scratch_dpart = nullptr;  // degrid partial sums, one per tile entry (inside scratch)
     bool bound = false;
     bool built = false;
     int64_t built_upto = 0;         // visibilities built so far, in build order
