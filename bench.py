@@ -43,9 +43,16 @@ def parse():
     ap.add_argument("--m-vis", type=int, default=None, help="override visibility count (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6)
-    ap.add_argument("--mode", default="operator", choices=["operator", "copy"],
+    ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving"],
                     help="operator: the metric; copy: a plain 2 GiB device copy used to "
-                         "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
+                         "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE readings; serving: "
+                         "Poisson request stream from several imaging jobs")
+    ap.add_argument("--serve-jobs", type=int, default=8)
+    ap.add_argument("--serve-mmin", type=float, default=1e5)
+    ap.add_argument("--serve-mmax", type=float, default=2e6)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-load", type=float, default=0.75)
+    ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     return ap.parse_args()
 
 
@@ -121,6 +128,108 @@ def copy_calibration(steps: int):
                       "GB_s": 2 * nbytes / dt / 1e9}))
 
 
+def serving(args):
+    """Continuous-batching server fed by a seeded Poisson stream (see serving.py)."""
+    import torch
+
+    from paper_1903_06555_amd import synthetic as syn
+    from paper_1903_06555_amd import wsp
+    from paper_1903_06555_amd.serving import Server
+
+    rng = np.random.default_rng(5)
+    specs = []
+    for j in range(args.serve_jobs):
+        n = int(rng.choice([512, 1024, 2048, 4096]))
+        m = int(np.exp(rng.uniform(np.log(args.serve_mmin), np.log(args.serve_mmax))))
+        k = int(rng.integers(1, 17))
+        specs.append((f"job{j}", n, m, k, k > 1))
+    # one MWA-like track per job (30 min of rotation), first m visibilities
+    base = syn.mwa_rotation_uvw(int(max(s[2] for s in specs)), 1800.0)
+    srv = Server(hbm_budget=int(args.serve_budget_gb * 2**30))
+    t0 = time.perf_counter()
+    refused = []
+    for name, n, m, k, fold in specs:
+        params = wsp.make_params(n, math.radians(25.0), n_stacks=k, fold=fold)
+        try:
+            srv.register_job(name, params, base[:m])
+        except ValueError:
+            refused.append(name)
+        log(f"registered {name}: N={n} M={m} K={k} ({time.perf_counter() - t0:.1f} s)")
+    if srv.waiting_jobs:
+        raise RuntimeError("jobs left waiting at start; raise --serve-budget-gb")
+    live = [s for s in specs if s[0] not in refused]
+    dev = torch.device("cuda", 0)
+    inputs = {}
+    for name, n, m, k, fold in live:
+        inputs[name] = (torch.from_numpy(syn.point_source_sky(n, 200, "exp", 7)).float().to(dev),
+                        torch.from_numpy(syn.random_vis(m, 8)).to(torch.complex64).to(dev))
+    # capacity of the unbatched path: each request alone, back to back
+    t_alone = {}
+    for name, n, m, k, fold in live:
+        op = srv.jobs[name].op
+        for kind in ("forward", "adjoint"):
+            x, y = inputs[name]
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            for _ in range(3):
+                op.degrid(x) if kind == "forward" else op.grid(y)
+            torch.cuda.synchronize()
+            t_alone[(name, kind)] = (time.perf_counter() - tt) / 3
+    mean_service = float(np.mean(list(t_alone.values())))
+    rate = args.serve_load / mean_service
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, args.serve_requests))
+    plan = [(live[int(rng.integers(len(live)))][0], ("forward", "adjoint")[i % 2])
+            for i in range(args.serve_requests)]
+    log(f"offered load {args.serve_load:.2f} of unbatched capacity: {rate:.1f} req/s")
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    i = 0
+    reqs = []
+    while i < len(plan) or srv.queue or srv.inflight:
+        now = time.perf_counter() - start
+        while i < len(plan) and arrivals[i] <= now:
+            name, kind = plan[i]
+            x, y = inputs[name]
+            reqs.append(srv.submit(name, kind, x if kind == "forward" else y))
+            i += 1
+        srv.step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - start
+    vis = sum(srv.jobs[r.job_id].uvw.shape[0] for r in reqs)
+    unbatched_s = sum(t_alone[(r.job_id, r.kind)] for r in reqs)
+    lat = srv.latency_percentiles()
+    for name in list(srv.jobs):
+        if srv.jobs[name].op is not None:
+            srv.retire_job(name)
+    # the plain unbatched FP64 path on the same request plan, one job at a time
+    t64 = {}
+    for name, n, m, k, fold in live:
+        params = wsp.make_params(n, math.radians(25.0), n_stacks=k, fold=fold, precision="fp64")
+        op = wsp.Operator(params, base[:m])
+        x, y = inputs[name]
+        x, y = x.double(), y.to(torch.complex128)
+        for kind in ("forward", "adjoint"):
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            for _ in range(3):
+                op.degrid(x) if kind == "forward" else op.grid(y)
+            torch.cuda.synchronize()
+            t64[(name, kind)] = (time.perf_counter() - tt) / 3
+        op.close()
+        log(f"fp64 baseline {name} done")
+    unbatched64_s = sum(t64[(r.job_id, r.kind)] for r in reqs)
+    print(json.dumps({
+        "metric": "served operator requests: p50/p99 latency and Mvis/s",
+        "mode": "serving", "requests": len(reqs), "wall_s": wall,
+        "value": vis / wall / 1e6, "unit": "Mvis/s",
+        "latency_ms": lat, "offered_load": args.serve_load,
+        "unbatched_mvis_per_s": vis / unbatched_s / 1e6,
+        "unbatched_fp64_mvis_per_s": vis / unbatched64_s / 1e6,
+        "jobs": [{"name": a, "n": b, "m": c, "stacks": d} for a, b, c, d, _ in live],
+        "refused": refused, "dtype": "f32", "data": "synthetic",
+    }))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -128,6 +237,9 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         copy_calibration(args.steps)
+        return
+    if args.mode == "serving":
+        serving(args)
         return
 
     import torch

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64
                                                       typename Types<kFP64>::C *dpart, TileArgs t) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    constexpr int kU = 4;
+    constexpr int kU = 8;
     __shared__ C tile[kTile * kTile];
     __shared__ int4 s_ent[kChunk];
     __shared__ int s_idx[kChunk];
@@ -249,24 +249,21 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64
                 int li[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    const int k = k0 + 64 * u + lane;
+                    // past the sub-block: re-read tap 0 and weight it by zero below
+                    const int k = k0 + 64 * u + lane < ntap ? k0 + 64 * u + lane : 0;
                     // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
                     const int row = (int)(((float)k + 0.5f) * inv_nc);
                     const int col = k - row * nc;
-                    const bool ok = k < ntap;
-                    li[u] = ok ? (ly0 + row) * kTile + lx0 + col : 0;
-                    if (ok) {
-                        K[u] = tp[row * jp + col];
-                    } else {
-                        K[u].x = 0;
-                        K[u].y = 0;
-                    }
+                    li[u] = (ly0 + row) * kTile + lx0 + col;
+                    K[u] = tp[row * jp + col];
                 }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
+                    const bool ok = k0 + 64 * u + lane < ntap;
                     const C z = tile[li[u]];
-                    ar += K[u].x * z.x - K[u].y * z.y;
-                    ai += K[u].x * z.y + K[u].y * z.x;
+                    const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
+                    ar += kr * z.x - ki * z.y;
+                    ai += kr * z.y + ki * z.x;
                 }
             }
             ar = wave_sum_r(ar);
@@ -348,17 +345,26 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
             const int nc = en.z & 255, lx0 = (en.z >> 16) & 255;
             const int jp = s_jp[j];
             const bool colok = lane >= lx0 && lane < lx0 + nc;
-            // tap of tile cell (row, lane): entry row r0 + row - ly0, column c0 + lane - lx0
-            const C *tp = taps + s_off[j] + (int64_t)(r0 - ly0) * jp + (c0 - lx0) + lane;
+            // tap of tile cell (row, lane): entry row r0 + row - ly0, column c0 + lane - lx0.
+            // Cells outside the entry read the entry's first tap (always in range) and
+            // add zero, so all 16 loads are issued before the first use.
+            const C *first = taps + s_off[j];
+            const int64_t lane_off = (int64_t)(r0 - ly0) * jp + (c0 - lx0) + lane;
             const C y = s_y[j];
+            C K[kBand];
 #pragma unroll
             for (int r = 0; r < kBand; ++r) {
                 const int row = band0 + r;
-                if (row >= lo && row < hi && colok) {
-                    const C K = tp[(int64_t)row * jp];
-                    accr[r] += K.x * y.x + K.y * y.y;
-                    acci[r] += K.x * y.y - K.y * y.x;
-                }
+                const bool ok = row >= lo && row < hi && colok;
+                K[r] = first[ok ? lane_off + (int64_t)row * jp : 0];
+            }
+#pragma unroll
+            for (int r = 0; r < kBand; ++r) {
+                const int row = band0 + r;
+                const bool ok = row >= lo && row < hi && colok;
+                const R kr = ok ? K[r].x : (R)0, ki = ok ? K[r].y : (R)0;
+                accr[r] += kr * y.x + ki * y.y;
+                acci[r] += kr * y.y - ki * y.x;
             }
         }
     }
