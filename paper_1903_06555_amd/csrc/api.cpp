@@ -484,9 +484,19 @@ wsp_status wsp_kernel_values(wsp_ctx *c, int64_t p, void *out, int32_t *jp, int3
     if (u0) *u0 = (int32_t)((int64_t)std::floor(uu * c->g.inv_du) - j / 2 + 1);
     if (v0) *v0 = (int32_t)((int64_t)std::floor(vv * c->g.inv_du) - j / 2 + 1);
     if (out) {
+        // copy the visibility's block and undo the tile grouping (row-major out)
         const size_t cb = cplx_bytes(c);
-        HIP_OR_FAIL(hipMemcpy(out, (const char *)c->taps + off * cb, (size_t)j * j * cb,
+        int32_t uw = 0, vw = 0;
+        HIP_OR_FAIL(hipMemcpy(&uw, c->plan.u0w + sidx, sizeof(int32_t), hipMemcpyDeviceToHost), "u0w");
+        HIP_OR_FAIL(hipMemcpy(&vw, c->plan.v0w + sidx, sizeof(int32_t), hipMemcpyDeviceToHost), "v0w");
+        std::vector<char> blk((size_t)j * j * cb);
+        HIP_OR_FAIL(hipMemcpy(blk.data(), (const char *)c->taps + off * cb, blk.size(),
                               hipMemcpyDeviceToHost), "taps");
+        char *o = (char *)out;
+        for (int row = 0; row < j; ++row)
+            for (int col = 0; col < j; ++col)
+                std::memcpy(o + ((size_t)row * j + col) * cb,
+                            blk.data() + blocked_tap_index(row, col, j, uw, vw) * cb, cb);
     }
     return WSP_OK;
 }

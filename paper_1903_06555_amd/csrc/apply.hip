@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64
             const int nc = en.z & 255, nr = (en.z >> 8) & 255;
             const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
             const int jp = s_jp[j];
-            const C *tp = taps + s_off[j] + (int64_t)r0 * jp + c0;
+            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, jp);
             const float inv_nc = 1.0f / (float)nc;
             const int ntap = nr * nc;
             R ar = 0, ai = 0;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64
                     const int row = (int)(((float)k + 0.5f) * inv_nc);
                     const int col = k - row * nc;
                     li[u] = (ly0 + row) * kTile + lx0 + col;
-                    K[u] = tp[row * jp + col];
+                    K[u] = tp[k];  // the sub-block is contiguous, row-major
                 }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
@@ -348,15 +348,16 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
             // tap of tile cell (row, lane): entry row r0 + row - ly0, column c0 + lane - lx0.
             // Cells outside the entry read the entry's first tap (always in range) and
             // add zero, so all 16 loads are issued before the first use.
-            const C *first = taps + s_off[j];
-            const int64_t lane_off = (int64_t)(r0 - ly0) * jp + (c0 - lx0) + lane;
+            const C *first = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, jp);
+            // sub-block cell (row - ly0, lane - lx0), row-major with stride nc
+            const int64_t lane_off = (int64_t)(-ly0) * nc + (lane - lx0);
             const C y = s_y[j];
             C K[kBand];
 #pragma unroll
             for (int r = 0; r < kBand; ++r) {
                 const int row = band0 + r;
                 const bool ok = row >= lo && row < hi && colok;
-                K[r] = first[ok ? lane_off + (int64_t)row * jp : 0];
+                K[r] = first[ok ? lane_off + (int64_t)row * nc : 0];
             }
 #pragma unroll
             for (int r = 0; r < kBand; ++r) {

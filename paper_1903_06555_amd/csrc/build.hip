@@ -40,6 +40,7 @@ struct BuildArgs {
     int64_t m;
     const double *ux, *vx, *weff;
     const int32_t *jp;
+    const int32_t *u0w, *v0w;
     const int64_t *tap_off;
     void *taps;
     Geom g;
@@ -385,14 +386,17 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
             }
         }
     }
+    const int u0w = A.u0w[p], v0w = A.v0w[p];
 #pragma unroll
     for (int k = 0; k < kTapsPerLane; ++k) {
         int64_t t = cbase + (int64_t)k * kWave + lane;
         if (t < ntap) {
+            const int row = (int)(t / jp), col = (int)(t - (int64_t)(t / jp) * jp);
+            const int64_t pos = off + blocked_tap_index(row, col, jp, u0w, v0w);
             if constexpr (kFP64) {
-                ((double2 *)A.taps)[off + t] = make_double2(accr[k], acci[k]);
+                ((double2 *)A.taps)[pos] = make_double2(accr[k], acci[k]);
             } else {
-                ((float2 *)A.taps)[off + t] = make_float2((float)accr[k], (float)acci[k]);
+                ((float2 *)A.taps)[pos] = make_float2((float)accr[k], (float)acci[k]);
             }
         }
     }
@@ -422,6 +426,8 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s)
     A.vx = pl.vx;
     A.weff = pl.weff;
     A.jp = pl.jp;
+    A.u0w = pl.u0w;
+    A.v0w = pl.v0w;
     A.tap_off = pl.tap_off;
     A.taps = c->taps;
     A.g = c->g;

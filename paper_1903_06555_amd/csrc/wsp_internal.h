@@ -37,6 +37,29 @@ struct Geom {
     double slope;        // support slope s f (cells per wavelength of |w - wbar|)
 };
 
+// Tap layout.  A visibility's J_p x J_p taps occupy one contiguous block
+// (at tap_off[p]).  Inside it the taps are grouped by the 64 x 64 grid tile
+// they fall in (tiles of the wrapped footprint starting at (u0w, v0w)):
+// sub-blocks follow each other tile row by tile row, and each sub-block is
+// row-major.  A work item therefore streams each of its entries as one
+// contiguous run.
+__host__ __device__ inline int64_t blocked_entry_offset(int r0, int nr, int c0, int jp) {
+    return (int64_t)r0 * jp + (int64_t)nr * c0;
+}
+
+__host__ __device__ inline int64_t blocked_tap_index(int row, int col, int jp, int u0w, int v0w) {
+    const int tvy = (v0w + row) / kTile, tvx = (u0w + col) / kTile;
+    int r0 = tvy * kTile - v0w;
+    r0 = r0 < 0 ? 0 : r0;
+    int r1 = (tvy + 1) * kTile - v0w;
+    r1 = r1 > jp ? jp : r1;
+    int c0 = tvx * kTile - u0w;
+    c0 = c0 < 0 ? 0 : c0;
+    int c1 = (tvx + 1) * kTile - u0w;
+    c1 = c1 > jp ? jp : c1;
+    return blocked_entry_offset(r0, r1 - r0, c0, jp) + (int64_t)(row - r0) * (c1 - c0) + (col - c0);
+}
+
 // Library-owned, per-visibility plan.  "Caller" arrays are in the caller's
 // order; the others are in sorted (stack, tile) order.
 struct Plan {
