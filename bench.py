@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--m-vis", type=int, default=None, help="override visibility count (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6)
-    ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving"],
+    ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving", "build"],
                     help="operator: the metric; copy: a plain 2 GiB device copy used to "
                          "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE readings; serving: "
                          "Poisson request stream from several imaging jobs")
@@ -56,8 +56,37 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mwa_1024_single_stack.json")
+TRAFFIC_SOURCES = ("paper_1903_06555_amd/csrc/apply.hip", "paper_1903_06555_amd/csrc/wsp_internal.h")
+
+
+def source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str, m: int):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    readings (calibrated on a plain copy), or None if they were taken on other
+    kernel sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != source_digest() or rec.get("workload") != workload \
+            or rec.get("m_vis") != m:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def algorithmic_bytes(stage: str, taps: int, m: int, cells: int, cb: int) -> int:
-    """Bytes one launch must move at minimum (measurement).
+    """Bytes one launch must move at minimum.
 
     degrid: every tap once, the grid cells once, per visibility its base
     (8 B), weight (4 B) and output (cb B).  grid: the same with the
@@ -230,6 +259,45 @@ def serving(args):
     }))
 
 
+def build_rate(args):
+    """Kernel construction throughput (set-up and build, no operator steps)."""
+    import torch
+
+    from paper_1903_06555_amd import synthetic as syn
+    from paper_1903_06555_amd import wsp
+
+    wl = syn.WORKLOADS[args.workload]
+    m = args.m_vis or wl.m_vis
+    precision = args.precision or wl.precision
+    uvw = syn.workload_uvw(wl, m)
+    params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
+                             precision=precision)
+    t0 = time.perf_counter()
+    op = wsp.Operator(params, uvw, build=False)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    _, _, iters = op.stacks()
+    log(f"plan (fold, k-means {iters} iterations, sort, tile lists) {t_plan:.2f} s")
+    t0 = time.perf_counter()
+    op.build(part=max(1, m // 10),
+             progress=lambda d, n: log(f"built {d}/{n} kernels, {time.perf_counter() - t0:.1f} s"))
+    t_build = time.perf_counter() - t0
+    jp, _ = op.support()
+    panels, capped = op.quad_stats()
+    print(json.dumps({
+        "metric": "w-projection kernels built per second (adaptive quadrature, tol 1e-6)",
+        "mode": "build", "value": m / t_build, "unit": "vis/s", "dtype": "f32" if precision != "fp64" else "f64",
+        "config": {"workload": wl.name, "n": wl.n, "m_vis": m, "n_stacks": wl.n_stacks,
+                   "fold": wl.fold, "precision": precision},
+        "build_s": t_build, "plan_s": t_plan, "kmeans_iterations": iters,
+        "taps": int(np.sum(jp.astype(np.int64) ** 2)), "mean_jp": float(jp.mean()),
+        "max_jp": int(jp.max()), "quad_panels": panels, "quad_capped": capped,
+        "paper_context": "126.6e6 visibilities in 15 min on 50 nodes x 16 Xeon cores "
+                         "(140.7e3 vis/s), Sec. 4",
+    }))
+    op.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -240,6 +308,9 @@ def main():
         return
     if args.mode == "serving":
         serving(args)
+        return
+    if args.mode == "build":
+        build_rate(args)
         return
 
     import torch
@@ -326,7 +397,8 @@ def main():
                    "oversample": params.oversample, "kb_support": params.kb_support},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, wl.name, m),
                      "algorithmic_bytes": traffic, "avg_launch_ms": per_launch[dom]},
         "stages_ms_per_launch": per_launch,
         "setup": {"plan_s": t_plan, "build_s": t_build, "build_mvis_per_s": m / t_build / 1e6,
