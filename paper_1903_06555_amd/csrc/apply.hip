@@ -300,32 +300,39 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
     vis[a.perm[p]] = y;
 }
 
-// GC_k^dagger (grid), one block per work item, no atomics: each of the four
-// wavefronts owns a band of 16 tile rows and keeps them in registers (lane =
-// tile column); every wavefront walks all entries of the item and adds
-// conj(K) yw for the entry rows inside its band.  The tile is then stored
-// into the grid (the tile's only item) or into a partial-tile slot that
-// k_reduce_tiles sums in item order.
+// GC_k^dagger (grid), one block per work item, no atomics: the item's 64 x 64
+// tile accumulates in LDS, and wavefront w owns tile rows [16 w, 16 w + 16):
+// no other wavefront touches them.  Every wavefront walks all entries of the
+// item; for each it streams the taps of the entry rows inside its band (a
+// contiguous run of the row-major sub-block), lanes on consecutive taps, and
+// adds conj(K) yw to the owned cells.  The cells of one entry are distinct
+// and a wavefront's LDS accesses complete in order, so plain read-modify-
+// write is exact.  The tile is then stored into the grid (the tile's only
+// item) or into a partial-tile slot that k_reduce_tiles sums in item order.
 template <bool kFP64>
 __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
                                                     const typename Types<kFP64>::C *__restrict__ yw,
                                                     typename Types<kFP64>::C *grids, TileArgs t) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    __shared__ int4 s_ent[kChunk];
-    __shared__ int64_t s_off[kChunk];
-    __shared__ int s_jp[kChunk];
-    __shared__ C s_y[kChunk];
+    constexpr int kU = 8;
+    constexpr int kGChunk = 128;  // keeps the block within a quarter of the LDS
+    __shared__ C tile[kTile * kTile];
+    __shared__ int4 s_ent[kGChunk];
+    __shared__ int64_t s_off[kGChunk];
+    __shared__ int s_jp[kGChunk];
+    __shared__ C s_y[kGChunk];
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
     const int band0 = (threadIdx.x >> 6) * kBand;
-    R accr[kBand], acci[kBand];
-#pragma unroll
-    for (int r = 0; r < kBand; ++r) accr[r] = acci[r] = 0;
+    C zero;
+    zero.x = 0;
+    zero.y = 0;
+    for (int i = lane; i < kBand * kTile; i += 64) tile[band0 * kTile + i] = zero;
     const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
-    for (int base = s_beg; base < s_end; base += kChunk) {
-        const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
+    for (int base = s_beg; base < s_end; base += kGChunk) {
+        const int n = (s_end - base < kGChunk) ? s_end - base : kGChunk;
         __syncthreads();  // previous chunk consumed
         if ((int)threadIdx.x < n) {
             const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
@@ -344,28 +351,35 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
             const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
             const int nc = en.z & 255, lx0 = (en.z >> 16) & 255;
             const int jp = s_jp[j];
-            const bool colok = lane >= lx0 && lane < lx0 + nc;
-            // tap of tile cell (row, lane): entry row r0 + row - ly0, column c0 + lane - lx0.
-            // Cells outside the entry read the entry's first tap (always in range) and
-            // add zero, so all 16 loads are issued before the first use.
-            const C *first = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, jp);
-            // sub-block cell (row - ly0, lane - lx0), row-major with stride nc
-            const int64_t lane_off = (int64_t)(-ly0) * nc + (lane - lx0);
+            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, jp);
+            const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
+            const float inv_nc = 1.0f / (float)nc;
+            const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
             const C y = s_y[j];
-            C K[kBand];
+            for (int k0 = kbeg; k0 < kend; k0 += 64 * kU) {
+                C K[kU], z[kU];
+                int li[kU];
+                // past the run: re-read its first tap; that lane stores nothing
 #pragma unroll
-            for (int r = 0; r < kBand; ++r) {
-                const int row = band0 + r;
-                const bool ok = row >= lo && row < hi && colok;
-                K[r] = first[ok ? lane_off + (int64_t)row * nc : 0];
-            }
+                for (int u = 0; u < kU; ++u) {
+                    const int k = k0 + 64 * u + lane < kend ? k0 + 64 * u + lane : kbeg;
+                    // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
+                    const int row = (int)(((float)k + 0.5f) * inv_nc);
+                    li[u] = cell0 + row * kTile + (k - row * nc);
+                    K[u] = tp[k];
+                }
+                // all reads before all writes: the kU cells are distinct
 #pragma unroll
-            for (int r = 0; r < kBand; ++r) {
-                const int row = band0 + r;
-                const bool ok = row >= lo && row < hi && colok;
-                const R kr = ok ? K[r].x : (R)0, ki = ok ? K[r].y : (R)0;
-                accr[r] += kr * y.x + ki * y.y;
-                acci[r] += kr * y.y - ki * y.x;
+                for (int u = 0; u < kU; ++u) z[u] = tile[li[u]];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (k0 + 64 * u + lane < kend) {
+                        C o;
+                        o.x = z[u].x + (K[u].x * y.x + K[u].y * y.y);
+                        o.y = z[u].y + (K[u].x * y.y - K[u].y * y.x);
+                        tile[li[u]] = o;
+                    }
+                }
             }
         }
     }
@@ -379,13 +393,9 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
         dst = (C *)t.partial + (int64_t)t.item_slot[item] * kTile * kTile;
         ld = kTile;
     }
+    // the band was written by this wavefront only: no barrier needed
 #pragma unroll
-    for (int r = 0; r < kBand; ++r) {
-        C v;
-        v.x = accr[r];
-        v.y = acci[r];
-        dst[(int64_t)(band0 + r) * ld + lane] = v;
-    }
+    for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(band0 + r) * kTile + lane];
 }
 
 // Sum the partial tiles of each tile shared by several items, in item order
