@@ -7,6 +7,8 @@
 //           stacks (k_crop_untaper).
 // Both sparse steps work on the tile work lists of the plan: each work item
 // is a run of (visibility, 64 x 64 grid tile) entries of one tile.
+#include <type_traits>
+
 #include "wsp_devmath.h"
 
 namespace wsp {
@@ -192,21 +194,61 @@ __device__ __forceinline__ C *tile_origin(C *grids, uint32_t key, const TileArgs
     return grids + (int64_t)k * t.G * t.G + (int64_t)ty * kTile * t.G + (int64_t)tx * kTile;
 }
 
-constexpr int kChunk = 256;           // entries whose metadata is staged in LDS at a time
-constexpr int kBand = kTile / 4;      // tile rows owned by each of the 4 wavefronts
+constexpr int kWaves = 8;             // wavefronts per block of the tile kernels
+constexpr int kThreads = 64 * kWaves;
+constexpr int kChunk = 256;           // degrid: entries whose metadata is staged in LDS at a time
+constexpr int kGChunk = 128;          // grid: the same (smaller: the block also holds y per entry)
+constexpr int kBand = kTile / kWaves; // grid: tile rows owned by each wavefront
+
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+
+// Tap loads: every tap is read once per operator application, so they are
+// issued non-temporal and do not evict reused data (the staged grid tiles)
+// from the caches.
+__device__ __forceinline__ float2 load_tap(const float2 *p) {
+    const v2f_t t = __builtin_nontemporal_load((const v2f_t *)p);
+    return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ double2 load_tap(const double2 *p) {
+    const v2d_t t = __builtin_nontemporal_load((const v2d_t *)p);
+    return make_double2(t.x, t.y);
+}
+
+// Batches of U x 64 consecutive taps of a run: 8 while at least 6 blocks of
+// 64 taps are left, then 4, 2, 1, so a run's tail issues few redundant loads
+// and the bulk keeps 8 loads per lane in flight.
+template <typename F>
+__device__ __forceinline__ void for_batches(int kbeg, int kend, F &&f) {
+    for (int k0 = kbeg; k0 < kend;) {
+        const int nb = (kend - k0 + 63) >> 6;  // uniform over the wavefront
+        if (nb >= 6) {
+            f(k0, std::integral_constant<int, 8>());
+            k0 += 512;
+        } else if (nb >= 3) {
+            f(k0, std::integral_constant<int, 4>());
+            k0 += 256;
+        } else if (nb == 2) {
+            f(k0, std::integral_constant<int, 2>());
+            k0 += 128;
+        } else {
+            f(k0, std::integral_constant<int, 1>());
+            k0 += 64;
+        }
+    }
+}
 
 // GC_k, W_k (degrid), one block per work item: the item's 64 x 64 grid tile
-// is staged in LDS; the four wavefronts take entries in turn, lanes walk the
+// is staged in LDS; the wavefronts take entries in turn, lanes walk the
 // entry's tap sub-block, multiply by the staged grid values and reduce; each
 // entry's partial sum goes to dpart[entry] (entries are stored grouped by
 // visibility), summed per visibility by k_degrid_reduce.
 template <bool kFP64>
-__global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
-                                                      const typename Types<kFP64>::C *__restrict__ grids,
-                                                      typename Types<kFP64>::C *dpart, TileArgs t) {
+__global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+                                                           const typename Types<kFP64>::C *__restrict__ grids,
+                                                           typename Types<kFP64>::C *dpart, TileArgs t) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    constexpr int kU = 8;
     __shared__ C tile[kTile * kTile];
     __shared__ int4 s_ent[kChunk];
     __shared__ int s_idx[kChunk];
@@ -216,7 +258,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64
     if (item >= t.n_items) return;  // uniform over the block
     {
         const C *src = tile_origin(grids, t.item_key[item], t);
-        for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x)
+        for (int i = threadIdx.x; i < kTile * kTile; i += kThreads)
             tile[i] = src[(int64_t)(i / kTile) * t.G + (i % kTile)];
     }
     const int lane = threadIdx.x & 63;
@@ -225,47 +267,47 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(const typename Types<kFP64
     for (int base = s_beg; base < s_end; base += kChunk) {
         const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
         __syncthreads();  // tile staged / previous chunk consumed
-        if ((int)threadIdx.x < n) {
-            const int e = t.ent_sorted[base + threadIdx.x];
+        for (int q = threadIdx.x; q < n; q += kThreads) {
+            const int e = t.ent_sorted[base + q];
             const int4 en = t.ent[e];
-            s_ent[threadIdx.x] = en;
-            s_idx[threadIdx.x] = e;
-            s_off[threadIdx.x] = t.tap_off[en.x];
-            s_jp[threadIdx.x] = t.jp[en.x];
+            s_ent[q] = en;
+            s_idx[q] = e;
+            s_off[q] = t.tap_off[en.x];
+            s_jp[q] = t.jp[en.x];
         }
         __syncthreads();
-        for (int j = wid; j < n; j += 4) {
+        for (int j = wid; j < n; j += kWaves) {
             const int4 en = s_ent[j];
             const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
             const int nc = en.z & 255, nr = (en.z >> 8) & 255;
             const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
-            const int jp = s_jp[j];
-            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, jp);
+            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, s_jp[j]);
             const float inv_nc = 1.0f / (float)nc;
             const int ntap = nr * nc;
+            const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
             R ar = 0, ai = 0;
-            for (int k0 = 0; k0 < ntap; k0 += 64 * kU) {
-                C K[kU];
-                int li[kU];
+            for_batches(0, ntap, [&](int k0, auto ucount) {
+                constexpr int U = decltype(ucount)::value;
+                C K[U];
+                int li[U];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < U; ++u) {
                     // past the sub-block: re-read tap 0 and weight it by zero below
                     const int k = k0 + 64 * u + lane < ntap ? k0 + 64 * u + lane : 0;
                     // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
                     const int row = (int)(((float)k + 0.5f) * inv_nc);
-                    const int col = k - row * nc;
-                    li[u] = (ly0 + row) * kTile + lx0 + col;
-                    K[u] = tp[k];  // the sub-block is contiguous, row-major
+                    li[u] = cell0 + row * kTile + (k - row * nc);
+                    K[u] = load_tap(&tp[k]);  // the sub-block is contiguous, row-major
                 }
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < U; ++u) {
                     const bool ok = k0 + 64 * u + lane < ntap;
                     const C z = tile[li[u]];
                     const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
                     ar += kr * z.x - ki * z.y;
                     ai += kr * z.y + ki * z.x;
                 }
-            }
+            });
             ar = wave_sum_r(ar);
             ai = wave_sum_r(ai);
             if (lane == 0) {
@@ -301,8 +343,8 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
 }
 
 // GC_k^dagger (grid), one block per work item, no atomics: the item's 64 x 64
-// tile accumulates in LDS, and wavefront w owns tile rows [16 w, 16 w + 16):
-// no other wavefront touches them.  Every wavefront walks all entries of the
+// tile accumulates in LDS, and wavefront w owns tile rows [8 w, 8 w + 8): no
+// other wavefront touches them.  Every wavefront walks all entries of the
 // item; for each it streams the taps of the entry rows inside its band (a
 // contiguous run of the row-major sub-block), lanes on consecutive taps, and
 // adds conj(K) yw to the owned cells.  The cells of one entry are distinct
@@ -310,18 +352,16 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
 // write is exact.  The tile is then stored into the grid (the tile's only
 // item) or into a partial-tile slot that k_reduce_tiles sums in item order.
 template <bool kFP64>
-__global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
-                                                    const typename Types<kFP64>::C *__restrict__ yw,
-                                                    typename Types<kFP64>::C *grids, TileArgs t) {
-    using R = typename Types<kFP64>::R;
+__global__ __launch_bounds__(kThreads) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+                                                         const typename Types<kFP64>::C *__restrict__ yw,
+                                                         typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
-    constexpr int kU = 8;
-    constexpr int kGChunk = 128;  // keeps the block within a quarter of the LDS
     __shared__ C tile[kTile * kTile];
     __shared__ int4 s_ent[kGChunk];
     __shared__ int64_t s_off[kGChunk];
     __shared__ int s_jp[kGChunk];
     __shared__ C s_y[kGChunk];
+    static_assert(kGChunk <= kThreads, "one thread stages one entry");
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
@@ -350,29 +390,28 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
             if (lo >= hi) continue;  // no entry row in this band (uniform)
             const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
             const int nc = en.z & 255, lx0 = (en.z >> 16) & 255;
-            const int jp = s_jp[j];
-            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, jp);
+            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, s_jp[j]);
             const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
             const float inv_nc = 1.0f / (float)nc;
             const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
             const C y = s_y[j];
-            for (int k0 = kbeg; k0 < kend; k0 += 64 * kU) {
-                C K[kU], z[kU];
-                int li[kU];
+            for_batches(kbeg, kend, [&](int k0, auto ucount) {
+                constexpr int U = decltype(ucount)::value;
+                C K[U], z[U];
+                int li[U];
                 // past the run: re-read its first tap; that lane stores nothing
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < U; ++u) {
                     const int k = k0 + 64 * u + lane < kend ? k0 + 64 * u + lane : kbeg;
-                    // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
-                    const int row = (int)(((float)k + 0.5f) * inv_nc);
+                    const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in degrid
                     li[u] = cell0 + row * kTile + (k - row * nc);
-                    K[u] = tp[k];
+                    K[u] = load_tap(&tp[k]);
                 }
-                // all reads before all writes: the kU cells are distinct
+                // all reads before all writes: the U x 64 cells are distinct
 #pragma unroll
-                for (int u = 0; u < kU; ++u) z[u] = tile[li[u]];
+                for (int u = 0; u < U; ++u) z[u] = tile[li[u]];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < U; ++u) {
                     if (k0 + 64 * u + lane < kend) {
                         C o;
                         o.x = z[u].x + (K[u].x * y.x + K[u].y * y.y);
@@ -380,7 +419,7 @@ __global__ __launch_bounds__(256) void k_grid_tiles(const typename Types<kFP64>:
                         tile[li[u]] = o;
                     }
                 }
-            }
+            });
         }
     }
     const uint32_t key = t.item_key[item];
@@ -484,7 +523,7 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     ev = stage_begin(c, s);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        hipLaunchKernelGGL(k_degrid_tiles<kFP64>, dim3(nb), dim3(256), 0, s, (const C *)c->taps,
+        hipLaunchKernelGGL(k_degrid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
                            (const C *)c->grids, (C *)c->scratch_dpart, ta);
     }
     hipLaunchKernelGGL(k_degrid_reduce<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s,
@@ -512,7 +551,7 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
                        (C *)c->scratch_yw, a);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        hipLaunchKernelGGL(k_grid_tiles<kFP64>, dim3(nb), dim3(256), 0, s, (const C *)c->taps,
+        hipLaunchKernelGGL(k_grid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
                            (const C *)c->scratch_yw, (C *)c->grids, ta);
     }
     if (pl.n_mtiles > 0) {

@@ -30,7 +30,12 @@ namespace wsp {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kTapsPerLane = 8;
+// taps per lane of the tap kernel: fewer on the FP64 path, whose per-tap
+// state is twice as wide, so that more than one wavefront fits per SIMD
+template <bool kFP64>
+constexpr int taps_per_lane() {
+    return kFP64 ? 4 : 8;
+}
 constexpr int kPanelGroup = 4;                 // panels per node batch (60 of 64 lanes)
 constexpr int kGroupNodes = kPanelGroup * WSP_GK_N;
 constexpr int64_t kBuildBatch = 65536;    // visibilities per partition batch
@@ -270,13 +275,15 @@ __global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, 
     }
 }
 
-// Phase 2 kernel: one wavefront per (visibility, chunk of 64 kTapsPerLane
-// taps); unit_off is the exclusive prefix of chunks per visibility.
+// Phase 2 kernel: one wavefront per (visibility, chunk of 64 x
+// taps_per_lane taps); unit_off is the exclusive prefix of chunks per
+// visibility.
 template <bool kFP64>
 __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int nb,
                                               const float *__restrict__ part,
                                               const int *__restrict__ npan,
                                               const int *__restrict__ unit_off, int nunits) {
+    constexpr int kTapsPerLane = taps_per_lane<kFP64>();
     const int lane = threadIdx.x & (kWave - 1);
     const int unit = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (unit >= nunits) return;
@@ -301,6 +308,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
 
     double q[kTapsPerLane];
     float qf[kTapsPerLane], qinv[kTapsPerLane], qrs[kTapsPerLane];
+    double qinv64[kTapsPerLane], qrs64[kTapsPerLane];
     double accr[kTapsPerLane], acci[kTapsPerLane];
 #pragma unroll
     for (int k = 0; k < kTapsPerLane; ++k) {
@@ -313,6 +321,10 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         // per-tap factors of 8 / x and sqrt(2 / (pi x)) (unused when q = 0)
         qinv[k] = q[k] > 0.0 ? (float)(1.0 / q[k]) : 0.0f;
         qrs[k] = q[k] > 0.0 ? (float)(1.0 / sqrt(q[k])) : 0.0f;
+        if constexpr (kFP64) {
+            qinv64[k] = q[k] > 0.0 ? 1.0 / q[k] : 0.0;
+            qrs64[k] = q[k] > 0.0 ? 1.0 / sqrt(q[k]) : 0.0;
+        }
         accr[k] = acci[k] = 0.0;
     }
     for (int pg = 0; pg < P; pg += kPanelGroup) {
@@ -333,16 +345,20 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         }
         const int nn = (P - pg >= kPanelGroup ? kPanelGroup : P - pg) * WSP_GK_N;
         if constexpr (kFP64) {
+            // per-node factors of 8 / x and sqrt(2 / (pi x)), as in the FP32 branch
+            const double rinv64 = nr > 0.0 ? 1.2732395447351627 / nr : 0.0;
+            const double rrs64 = nr > 0.0 ? 0.3183098861837907 / sqrt(nr) : 0.0;
             double pr[kTapsPerLane], pi_[kTapsPerLane];
 #pragma unroll
             for (int k = 0; k < kTapsPerLane; ++k) pr[k] = pi_[k] = 0.0;
             for (int n = 0; n < nn; ++n) {
                 const double rn = readlane_f64(nr, n);
                 const double are = readlane_f64(nre, n), aim = readlane_f64(nim, n);
+                const double ri = readlane_f64(rinv64, n), rr = readlane_f64(rrs64, n);
 #pragma unroll
                 for (int k = 0; k < kTapsPerLane; ++k) {
                     if (cbase + (int64_t)k * kWave < ntap) {
-                        double J = j0(kTwoPi * rn * q[k]);
+                        double J = j0_fp64(rn, q[k], ri * qinv64[k], rr * qrs64[k]);
                         pr[k] = fma(are, J, pr[k]);
                         pi_[k] = fma(aim, J, pi_[k]);
                     }
@@ -403,7 +419,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
 }
 
 __global__ void k_unit_counts(const int32_t *__restrict__ border, const int32_t *__restrict__ jp,
-                              int64_t batch0, int nb, int *cnt) {
+                              int64_t batch0, int nb, int64_t chunk, int *cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > nb) return;
     if (i == nb) {
@@ -411,7 +427,6 @@ __global__ void k_unit_counts(const int32_t *__restrict__ border, const int32_t 
         return;
     }
     int64_t j = jp[border[batch0 + i]];
-    const int64_t chunk = (int64_t)kWave * kTapsPerLane;
     cnt[i] = (int)((j * j + chunk - 1) / chunk);
 }
 
@@ -471,8 +486,10 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s)
         dim3 block(kWave * kWavesPerBlock);
         hipLaunchKernelGGL(k_partition, dim3((nb + kWavesPerBlock - 1) / kWavesPerBlock), block, 0,
                            s, A, b0, nb, part, npan);
+        const int64_t chunk = (int64_t)kWave * (c->p.precision == WSP_FP64 ? taps_per_lane<true>()
+                                                                           : taps_per_lane<false>());
         hipLaunchKernelGGL(k_unit_counts, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, pl.border,
-                           pl.jp, b0, nb, cnt);
+                           pl.jp, b0, nb, chunk, cnt);
         WSP_BSTEP(hipGetLastError());
         WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, uoff, nb + 1, s));
         int nunits = 0;

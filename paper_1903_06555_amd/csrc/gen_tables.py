@@ -214,6 +214,25 @@ def main():
     lines.append("#define WSP_SC_N 5")
     lines.append("static __constant__ float wsp_sin_c[] = {" + ", ".join(mp.nstr(v, 12) + "f" for v in cS) + "};")
     lines.append("static __constant__ float wsp_cos_c[] = {" + ", ".join(mp.nstr(v, 12) + "f" for v in cC) + "};")
+    # FP64 path: the same Hankel form and octant sine / cosine, fitted to FP64 accuracy
+    deg_l64 = 8
+    cP64 = fit_in_t(fP, deg_l64, tmin, mp.mpf(1))
+    cR64 = fit_in_t(fR, deg_l64, tmin, mp.mpf(1))
+    eP64 = max_err(fP, lambda t: horner(cP64, t), tmin, 1)
+    eR64 = max_err(fR, lambda t: horner(cR64, t), tmin, 1)
+    lines.append(f"/* FP64 path, x >= 8: P0 (err {mp.nstr(eP64, 3)}), Q0 / (8/x) (err {mp.nstr(eR64, 3)}), powers of t = (8/x)^2 */")
+    lines.append(f"#define WSP_J0L64_N {deg_l64 + 1}")
+    lines.append("static __constant__ double wsp_j0l_p64[] = {" + ", ".join(mp.nstr(v, 20) for v in cP64) + "};")
+    lines.append("static __constant__ double wsp_j0l_q64[] = {" + ", ".join(mp.nstr(v, 20) for v in cR64) + "};")
+    deg_sc64 = 6
+    cS64 = fit_in_t(fS, deg_sc64, mp.mpf(0), gmax2)
+    cC64 = fit_in_t(fC, deg_sc64, mp.mpf(0), gmax2)
+    eS64 = max_err(lambda g: mp.sin(2 * mp.pi * g), lambda g: g * horner(cS64, g * g), 0, mp.mpf(1) / 8)
+    eC64 = max_err(lambda g: mp.cos(2 * mp.pi * g), lambda g: horner(cC64, g * g), 0, mp.mpf(1) / 8)
+    lines.append(f"/* FP64 path: sin(2 pi g) = g sum s_k g^2k (err {mp.nstr(eS64, 3)}), cos(2 pi g) = sum c_k g^2k (err {mp.nstr(eC64, 3)}), |g| <= 1/8 */")
+    lines.append(f"#define WSP_SC64_N {deg_sc64 + 1}")
+    lines.append("static __constant__ double wsp_sin_c64[] = {" + ", ".join(mp.nstr(v, 20) for v in cS64) + "};")
+    lines.append("static __constant__ double wsp_cos_c64[] = {" + ", ".join(mp.nstr(v, 20) for v in cC64) + "};")
     # reciprocals 1 / ((k + 1) (k + 2)) for the power series of I1(z) / z in z^2 / 4
     lines.append("/* 1 / ((k + 1) (k + 2)), k = 0..127: ratio of successive terms of sum_k y^k / (k! (k+1)!) */")
     lines.append("#define WSP_SERIES_N 128")

@@ -58,6 +58,70 @@ __device__ __forceinline__ void sincos_rev(float f, float *sn, float *cs) {
     *cs = ((q + 1) & 2) ? -c1 : c1;
 }
 
+// J0(x), 0 <= x < 8: Chebyshev series in u = 2 (x/8)^2 - 1, FP64 Clenshaw.
+__device__ __forceinline__ double j0_small(double x) {
+    double u = fma(x * x, 1.0 / 32.0, -1.0);
+    double u2 = 2.0 * u;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int j = WSP_J0S_N - 1; j >= 1; --j) {
+        double b0 = fma(u2, b1, wsp_j0s_c[j] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(u, b1, wsp_j0s_c[0] - b2);
+}
+
+// Fraction of r q - 1/8 revolutions in [-1/2, 1/2]: the phase of the Hankel
+// form, (x - pi/4) / (2 pi) with x = 2 pi r q.  Round-to-nearest by the
+// 1.5 * 2^52 shift (|r q| < 2^51).
+__device__ __forceinline__ double hankel_phase_rev(double r, double q) {
+    const double kShift = 6755399441055744.0;
+    double s = fma(r, q, -0.125);
+    double k = (s + kShift) - kShift;
+    return s - k;
+}
+
+// sin(2 pi f), cos(2 pi f) for |f| <= 1/2 in FP64 (octant polynomials).
+__device__ __forceinline__ void sincos_rev64(double f, double *sn, double *cs) {
+    double k4 = rint(4.0 * f);
+    double gg = fma(-0.25, k4, f);  // |gg| <= 1/8
+    double g2 = gg * gg;
+    double s = wsp_sin_c64[WSP_SC64_N - 1];
+    double c = wsp_cos_c64[WSP_SC64_N - 1];
+#pragma unroll
+    for (int i = WSP_SC64_N - 2; i >= 0; --i) {
+        s = fma(s, g2, wsp_sin_c64[i]);
+        c = fma(c, g2, wsp_cos_c64[i]);
+    }
+    s *= gg;
+    int q = ((int)k4) & 3;
+    double s1 = (q & 1) ? c : s;
+    double c1 = (q & 1) ? s : c;
+    *sn = (q & 2) ? -s1 : s1;
+    *cs = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// J0(2 pi r q) for the FP64 path: the split of j0_fp64phase, every step in
+// FP64.  inv = 8 / x and amp = sqrt(2 / (pi x)) come from per-node and
+// per-tap factors, as there.
+__device__ __forceinline__ double j0_fp64(double r, double q, double inv, double amp) {
+    double x = kTwoPi * (r * q);
+    if (x < 8.0) return j0_small(x);
+    double sn, cs;
+    sincos_rev64(hankel_phase_rev(r, q), &sn, &cs);
+    double t = inv * inv;
+    double P = wsp_j0l_p64[WSP_J0L64_N - 1];
+    double Q = wsp_j0l_q64[WSP_J0L64_N - 1];
+#pragma unroll
+    for (int i = WSP_J0L64_N - 2; i >= 0; --i) {
+        P = fma(P, t, wsp_j0l_p64[i]);
+        Q = fma(Q, t, wsp_j0l_q64[i]);
+    }
+    Q *= inv;
+    return amp * (P * cs - Q * sn);
+}
+
 // J0(2 pi r q) for the FP32 path.
 //   x < 8:  Chebyshev series in FP64 (no transcendental; an FP64 FMA issues
 //           at the FP32 rate on CDNA without packed math);
@@ -68,24 +132,8 @@ __device__ __forceinline__ void sincos_rev(float f, float *sn, float *cs) {
 // FP32, formed from per-node and per-tap factors so that no division or
 // square root is needed per evaluation.
 __device__ __forceinline__ float j0_fp64phase(double r, double q, float xf, float inv, float amp) {
-    if (xf < 8.0f) {
-        double x = kTwoPi * (r * q);
-        double u = fma(x * x, 1.0 / 32.0, -1.0);
-        double u2 = 2.0 * u;
-        double b1 = 0.0, b2 = 0.0;
-#pragma unroll
-        for (int j = WSP_J0S_N - 1; j >= 1; --j) {
-            double b0 = fma(u2, b1, wsp_j0s_c[j] - b2);
-            b2 = b1;
-            b1 = b0;
-        }
-        return (float)fma(u, b1, wsp_j0s_c[0] - b2);
-    }
-    // round-to-nearest by the 1.5 * 2^52 shift (|r q| < 2^51)
-    const double kShift = 6755399441055744.0;
-    double s = fma(r, q, -0.125);
-    double k = (s + kShift) - kShift;
-    float f = (float)(s - k);
+    if (xf < 8.0f) return (float)j0_small(kTwoPi * (r * q));
+    float f = (float)hankel_phase_rev(r, q);
     // hardware sine / cosine of f revolutions (|f| <= 1/2; measured max error
     // 1.3e-7 on gfx950 against FP64, same order as FP32 rounding of the result)
     float sn = __builtin_amdgcn_sinf(f);
