@@ -36,18 +36,16 @@ __device__ __forceinline__ C cmul(C a, C b) {
     return o;
 }
 
-// exp(-2 pi i wbar (n - 1)) / (g(r) n) for pixel (j, i): returns (magnitude,
-// reduced phase in revolutions).  r = rho du cycles per cell.
-__device__ __forceinline__ void stack_correction(int j, int i, double wbar, const Geom &g,
-                                                 double *amp, double *rev) {
+// Per-pixel factors of S~_k (Eq. 4): 1 / (g(r) n) and n - 1 at pixel (j, i),
+// r = rho du cycles per cell; the stack enters only through the phase
+// -wbar_k (n - 1) revolutions.
+__device__ __forceinline__ void pixel_factors(int j, int i, const Geom &g, double *amp, double *nm1) {
     double l = (double)(i - g.n / 2) * g.dl;
     double m = (double)(j - g.n / 2) * g.dl;
     double rho2 = l * l + m * m;
-    double nm1 = n_minus_one(rho2);
-    double n = 1.0 + nm1;
+    *nm1 = n_minus_one(rho2);
     double gv = taper_g(sqrt(rho2) * g.du, g);
-    *amp = 1.0 / (gv * n);
-    *rev = reduce_rev(-wbar * nm1);
+    *amp = 1.0 / (gv * (1.0 + *nm1));
 }
 
 template <bool kFP64>
@@ -68,6 +66,7 @@ __device__ __forceinline__ int pixel_of(int V, const Geom &g) {
     return -1;
 }
 
+// S~_k and Z for all stacks: one thread per grid cell, looping over stacks.
 template <bool kFP64>
 __global__ void k_taper_pad(const typename Types<kFP64>::R *__restrict__ image,
                             typename Types<kFP64>::C *grids, const double *__restrict__ centres,
@@ -75,27 +74,30 @@ __global__ void k_taper_pad(const typename Types<kFP64>::R *__restrict__ image,
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     const int64_t GG = (int64_t)g.G * g.G;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= GG * g.n_stacks) return;
-    int k = (int)(idx / GG);
-    int64_t cell = idx - (int64_t)k * GG;
+    int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= GG) return;
     int V = (int)(cell / g.G), U = (int)(cell - (int64_t)V * g.G);
     int j = pixel_of(V, g), i = pixel_of(U, g);
     C z;
     z.x = 0;
     z.y = 0;
-    if (j >= 0 && i >= 0) {
-        double amp, rev;
-        stack_correction(j, i, centres[k], g, &amp, &rev);
+    if (j < 0 || i < 0) {
+        for (int k = 0; k < g.n_stacks; ++k) grids[k * GG + cell] = z;
+        return;
+    }
+    double amp, nm1;
+    pixel_factors(j, i, g, &amp, &nm1);
+    const R a = (R)((double)image[(int64_t)j * g.n + i] * amp);
+    for (int k = 0; k < g.n_stacks; ++k) {
         R sn, cs;
-        rev_sincos<kFP64>(rev, &sn, &cs);
-        R a = (R)((double)image[(int64_t)j * g.n + i] * amp);
+        rev_sincos<kFP64>(reduce_rev(-centres[k] * nm1), &sn, &cs);
         z.x = a * cs;
         z.y = a * sn;
+        grids[k * GG + cell] = z;
     }
-    grids[idx] = z;
 }
 
+// Z^dagger, S~_k^dagger, Re and the sum over stacks: one thread per pixel.
 template <bool kFP64>
 __global__ void k_crop_untaper(const typename Types<kFP64>::C *__restrict__ grids,
                                typename Types<kFP64>::R *image, const double *__restrict__ centres,
@@ -106,17 +108,17 @@ __global__ void k_crop_untaper(const typename Types<kFP64>::C *__restrict__ grid
     int j = (int)(idx / g.n), i = (int)(idx - (int64_t)j * g.n);
     int V = (j - g.n / 2 + g.G) % g.G, U = (i - g.n / 2 + g.G) % g.G;
     const int64_t GG = (int64_t)g.G * g.G;
+    double amp, nm1;
+    pixel_factors(j, i, g, &amp, &nm1);
     double acc = 0.0;
     for (int k = 0; k < g.n_stacks; ++k) {
-        double amp, rev;
-        stack_correction(j, i, centres[k], g, &amp, &rev);
         R sn, cs;
-        rev_sincos<kFP64>(rev, &sn, &cs);
+        rev_sincos<kFP64>(reduce_rev(-centres[k] * nm1), &sn, &cs);
         auto z = grids[k * GG + (int64_t)V * g.G + U];
         // Re(z conj(s_k)) with s_k = amp e^{2 pi i rev}
-        acc += amp * (double)(z.x * cs + z.y * sn);
+        acc += (double)(z.x * cs + z.y * sn);
     }
-    image[idx] = (R)acc;
+    image[idx] = (R)(amp * acc);
 }
 
 template <typename C>
@@ -199,6 +201,7 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kChunk = 256;           // degrid: entries whose metadata is staged in LDS at a time
 constexpr int kGChunk = 128;          // grid: the same (smaller: the block also holds y per entry)
 constexpr int kBand = kTile / kWaves; // grid: tile rows owned by each wavefront
+constexpr int64_t kSmallEntryTaps = 160;  // mean taps per entry below which k_degrid_small / k_grid_small run
 
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef double v2d_t __attribute__((ext_vector_type(2)));
@@ -213,6 +216,16 @@ __device__ __forceinline__ float2 load_tap(const float2 *p) {
 __device__ __forceinline__ double2 load_tap(const double2 *p) {
     const v2d_t t = __builtin_nontemporal_load((const v2d_t *)p);
     return make_double2(t.x, t.y);
+}
+
+// value of lane l (l uniform over the wavefront)
+__device__ __forceinline__ float bcast(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double bcast(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
 }
 
 // Batches of U x 64 consecutive taps of a run: 8 while at least 6 blocks of
@@ -320,6 +333,95 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
     }
 }
 
+// Degrid for work lists of small entries (a few tens of taps, as with many
+// w-stacks): 16-lane groups take one entry each, so a wavefront reduces 4
+// entries per pass instead of spreading one entry over 64 lanes.  Otherwise
+// as k_degrid_tiles.
+constexpr int kGroup = 16;
+template <bool kFP64>
+__global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<kFP64>::C *__restrict__ taps,
+                                                           const typename Types<kFP64>::C *__restrict__ grids,
+                                                           typename Types<kFP64>::C *dpart, TileArgs t) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    constexpr int kPer = 64 / kGroup;  // entries per wavefront pass
+    constexpr int kU = 2;              // loads per lane in flight
+    __shared__ C tile[kTile * kTile];
+    __shared__ int4 s_ent[kChunk];
+    __shared__ int s_idx[kChunk];
+    __shared__ int64_t s_off[kChunk];
+    __shared__ int s_jp[kChunk];
+    const int item = xcd_item(blockIdx.x, t.n_items);
+    if (item >= t.n_items) return;  // uniform over the block
+    {
+        const C *src = tile_origin(grids, t.item_key[item], t);
+        for (int i = threadIdx.x; i < kTile * kTile; i += kThreads)
+            tile[i] = src[(int64_t)(i / kTile) * t.G + (i % kTile)];
+    }
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int grp = lane / kGroup, gl = lane % kGroup;
+    const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
+    for (int base = s_beg; base < s_end; base += kChunk) {
+        const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
+        __syncthreads();  // tile staged / previous chunk consumed
+        for (int q = threadIdx.x; q < n; q += kThreads) {
+            const int e = t.ent_sorted[base + q];
+            const int4 en = t.ent[e];
+            s_ent[q] = en;
+            s_idx[q] = e;
+            s_off[q] = t.tap_off[en.x];
+            s_jp[q] = t.jp[en.x];
+        }
+        __syncthreads();
+        for (int j0 = wid * kPer; j0 < n; j0 += kWaves * kPer) {
+            const int j = j0 + grp;
+            const bool valid = j < n;
+            const int4 en = s_ent[valid ? j : j0];
+            const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
+            const int nc = en.z & 255, nr = (en.z >> 8) & 255;
+            const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
+            const C *tp = taps + s_off[valid ? j : j0] + blocked_entry_offset(r0, nr, c0, s_jp[valid ? j : j0]);
+            const float inv_nc = 1.0f / (float)nc;
+            const int ntap = valid ? nr * nc : 0;
+            const int cell0 = ly0 * kTile + lx0;
+            R ar = 0, ai = 0;
+            for (int k0 = 0; __any(k0 < ntap); k0 += kGroup * kU) {
+                C K[kU];
+                int li[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    // past the entry: re-read its tap 0 and weight it by zero below
+                    const int k = k0 + kGroup * u + gl < ntap ? k0 + kGroup * u + gl : 0;
+                    const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in k_degrid_tiles
+                    li[u] = cell0 + row * kTile + (k - row * nc);
+                    K[u] = load_tap(&tp[k]);
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const bool ok = k0 + kGroup * u + gl < ntap;
+                    const C z = tile[li[u]];
+                    const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
+                    ar += kr * z.x - ki * z.y;
+                    ai += kr * z.y + ki * z.x;
+                }
+            }
+            // sum over the 16 lanes of the group
+#pragma unroll
+            for (int o = kGroup / 2; o > 0; o >>= 1) {
+                ar += __shfl_xor(ar, o, 64);
+                ai += __shfl_xor(ai, o, 64);
+            }
+            if (gl == 0 && valid) {
+                C o;
+                o.x = ar;
+                o.y = ai;
+                dpart[s_idx[j]] = o;
+            }
+        }
+    }
+}
+
 // y[perm[p]] = W_p (conj) sum of visibility p's entry partials, in entry order.
 template <bool kFP64>
 __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpart,
@@ -344,15 +446,15 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
 
 // GC_k^dagger (grid), one block per work item, no atomics: the item's 64 x 64
 // tile accumulates in LDS, and wavefront w owns tile rows [8 w, 8 w + 8): no
-// other wavefront touches them.  Every wavefront walks all entries of the
-// item; for each it streams the taps of the entry rows inside its band (a
-// contiguous run of the row-major sub-block), lanes on consecutive taps, and
-// adds conj(K) yw to the owned cells.  The cells of one entry are distinct
+// other wavefront touches them.  Every wavefront scans all entries of the
+// item (64 per ballot); for each entry with rows in its band it streams the
+// taps of those rows (a contiguous run of the row-major sub-block), lanes on
+// consecutive taps, and adds conj(K) yw to the owned cells.  The cells of one entry are distinct
 // and a wavefront's LDS accesses complete in order, so plain read-modify-
 // write is exact.  The tile is then stored into the grid (the tile's only
 // item) or into a partial-tile slot that k_reduce_tiles sums in item order.
 template <bool kFP64>
-__global__ __launch_bounds__(kThreads) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+__global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
                                                          const typename Types<kFP64>::C *__restrict__ yw,
                                                          typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
@@ -382,44 +484,191 @@ __global__ __launch_bounds__(kThreads) void k_grid_tiles(const typename Types<kF
             s_y[threadIdx.x] = yw[en.x];
         }
         __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            const int4 en = s_ent[j];
-            const int nr = (en.z >> 8) & 255, ly0 = (en.z >> 24) & 255;
-            const int lo = ly0 > band0 ? ly0 : band0;
-            const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
-            if (lo >= hi) continue;  // no entry row in this band (uniform)
-            const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
-            const int nc = en.z & 255, lx0 = (en.z >> 16) & 255;
-            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, s_jp[j]);
-            const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
-            const float inv_nc = 1.0f / (float)nc;
-            const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
-            const C y = s_y[j];
-            for_batches(kbeg, kend, [&](int k0, auto ucount) {
-                constexpr int U = decltype(ucount)::value;
-                C K[U], z[U];
-                int li[U];
-                // past the run: re-read its first tap; that lane stores nothing
+        // 64 entries at a time: lane l holds entry j0 + l; a ballot marks the
+        // entries with rows in this band, whose fields are then broadcast
+        // with readlane (no memory round trip per entry).
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            const int jl = j0 + lane;
+            int4 en_l = make_int4(0, 0, 0, 0);
+            int64_t off_l = 0;
+            int jp_l = 0;
+            C y_l = zero;
+            if (jl < n) {
+                en_l = s_ent[jl];
+                off_l = s_off[jl];
+                jp_l = s_jp[jl];
+                y_l = s_y[jl];
+            }
+            const int nr_l = (en_l.z >> 8) & 255, ly0_l = (en_l.z >> 24) & 255;
+            uint64_t hits = __ballot(jl < n && ly0_l < band0 + kBand && ly0_l + nr_l > band0);
+            while (hits) {
+                const int l = __builtin_ctzll(hits);
+                hits &= hits - 1;
+                const int ey = __builtin_amdgcn_readlane(en_l.y, l);
+                const int ez = __builtin_amdgcn_readlane(en_l.z, l);
+                const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
+                const int jp = __builtin_amdgcn_readlane(jp_l, l);
+                C y;
+                y.x = bcast(y_l.x, l);
+                y.y = bcast(y_l.y, l);
+                const int nr = (ez >> 8) & 255, ly0 = (ez >> 24) & 255;
+                const int lo = ly0 > band0 ? ly0 : band0;
+                const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
+                const int c0 = ey & 0xFFFF, r0 = (ey >> 16) & 0xFFFF;
+                const int nc = ez & 255, lx0 = (ez >> 16) & 255;
+                const C *tp = taps + off + blocked_entry_offset(r0, nr, c0, jp);
+                const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
+                const float inv_nc = 1.0f / (float)nc;
+                const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
+                for_batches(kbeg, kend, [&](int k0, auto ucount) {
+                    constexpr int U = decltype(ucount)::value;
+                    C K[U], z[U];
+                    int li[U];
+                    // past the run: re-read its first tap; that lane stores nothing
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int k = k0 + 64 * u + lane < kend ? k0 + 64 * u + lane : kbeg;
-                    const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in degrid
-                    li[u] = cell0 + row * kTile + (k - row * nc);
-                    K[u] = load_tap(&tp[k]);
-                }
-                // all reads before all writes: the U x 64 cells are distinct
+                    for (int u = 0; u < U; ++u) {
+                        const int k = k0 + 64 * u + lane < kend ? k0 + 64 * u + lane : kbeg;
+                        const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in degrid
+                        li[u] = cell0 + row * kTile + (k - row * nc);
+                        K[u] = load_tap(&tp[k]);
+                    }
+                    // all reads before all writes: the U x 64 cells are distinct
 #pragma unroll
-                for (int u = 0; u < U; ++u) z[u] = tile[li[u]];
+                    for (int u = 0; u < U; ++u) z[u] = tile[li[u]];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (k0 + 64 * u + lane < kend) {
-                        C o;
-                        o.x = z[u].x + (K[u].x * y.x + K[u].y * y.y);
-                        o.y = z[u].y + (K[u].x * y.y - K[u].y * y.x);
-                        tile[li[u]] = o;
+                    for (int u = 0; u < U; ++u) {
+                        if (k0 + 64 * u + lane < kend) {
+                            C o;
+                            o.x = z[u].x + (K[u].x * y.x + K[u].y * y.y);
+                            o.y = z[u].y + (K[u].x * y.y - K[u].y * y.x);
+                            tile[li[u]] = o;
+                        }
+                    }
+                });
+            }
+        }
+    }
+    const uint32_t key = t.item_key[item];
+    C *dst;
+    int64_t ld;
+    if (t.item_sole[item]) {
+        dst = tile_origin(grids, key, t);
+        ld = t.G;
+    } else {
+        dst = (C *)t.partial + (int64_t)t.item_slot[item] * kTile * kTile;
+        ld = kTile;
+    }
+    // the band was written by this wavefront only: no barrier needed
+#pragma unroll
+    for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(band0 + r) * kTile + lane];
+}
+
+// Grid for work lists of small entries: band ownership, ballot scan and
+// tile layout as in k_grid_tiles, but the band runs are short (a few tens of
+// taps), so one run per batch would keep one load per lane in flight.  Here
+// the loads of up to kSlots consecutive 64-tap slots (from any number of
+// runs) are issued together; then the slots are added into the tile one
+// after the other, in entry order (two entries may share cells).
+constexpr int kSlots = 8;
+template <bool kFP64>
+__global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_small(const typename Types<kFP64>::C *__restrict__ taps,
+                                                                        const typename Types<kFP64>::C *__restrict__ yw,
+                                                                        typename Types<kFP64>::C *grids, TileArgs t) {
+    using C = typename Types<kFP64>::C;
+    __shared__ C tile[kTile * kTile];
+    __shared__ int4 s_ent[kGChunk];
+    __shared__ int64_t s_off[kGChunk];
+    __shared__ int s_jp[kGChunk];
+    __shared__ C s_y[kGChunk];
+    const int item = xcd_item(blockIdx.x, t.n_items);
+    if (item >= t.n_items) return;  // uniform over the block
+    const int lane = threadIdx.x & 63;
+    const int band0 = (threadIdx.x >> 6) * kBand;
+    C zero;
+    zero.x = 0;
+    zero.y = 0;
+    for (int i = lane; i < kBand * kTile; i += 64) tile[band0 * kTile + i] = zero;
+    const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
+    for (int base = s_beg; base < s_end; base += kGChunk) {
+        const int n = (s_end - base < kGChunk) ? s_end - base : kGChunk;
+        __syncthreads();  // previous chunk consumed
+        if ((int)threadIdx.x < n) {
+            const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
+            s_ent[threadIdx.x] = en;
+            s_off[threadIdx.x] = t.tap_off[en.x];
+            s_jp[threadIdx.x] = t.jp[en.x];
+            s_y[threadIdx.x] = yw[en.x];
+        }
+        __syncthreads();
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            const int jl = j0 + lane;
+            int4 en_l = make_int4(0, 0, 0, 0);
+            int64_t off_l = 0;
+            int jp_l = 0;
+            C y_l = zero;
+            if (jl < n) {
+                en_l = s_ent[jl];
+                off_l = s_off[jl];
+                jp_l = s_jp[jl];
+                y_l = s_y[jl];
+            }
+            const int nr_l = (en_l.z >> 8) & 255, ly0_l = (en_l.z >> 24) & 255;
+            uint64_t hits = __ballot(jl < n && ly0_l < band0 + kBand && ly0_l + nr_l > band0);
+            // current run (uniform): taps [k0, kend) of the entry's rows in the
+            // band; the entry's y sits in lane yl of y_l
+            const C *tp = taps;
+            int k0 = 0, kend = 0, kbeg = 0, nc = 1, cell0 = 0, yl = 0;
+            float inv_nc = 1.0f;
+            while (hits || k0 < kend) {
+                C K[kSlots];
+                int li[kSlots], ys[kSlots];
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    li[sl] = -1;
+                    if (k0 >= kend && hits) {  // next entry with rows in the band
+                        const int l = __builtin_ctzll(hits);
+                        hits &= hits - 1;
+                        const int ey = __builtin_amdgcn_readlane(en_l.y, l);
+                        const int ez = __builtin_amdgcn_readlane(en_l.z, l);
+                        const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
+                        const int jp = __builtin_amdgcn_readlane(jp_l, l);
+                        yl = l;
+                        const int nr = (ez >> 8) & 255, ly0 = (ez >> 24) & 255;
+                        const int lo = ly0 > band0 ? ly0 : band0;
+                        const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
+                        nc = ez & 255;
+                        tp = taps + off + blocked_entry_offset((ey >> 16) & 0xFFFF, nr, ey & 0xFFFF, jp);
+                        kbeg = (lo - ly0) * nc;
+                        kend = (hi - ly0) * nc;
+                        k0 = kbeg;
+                        inv_nc = 1.0f / (float)nc;
+                        cell0 = ly0 * kTile + ((ez >> 16) & 255);
+                    }
+                    K[sl] = zero;
+                    ys[sl] = yl;
+                    if (k0 < kend) {  // uniform: this slot takes taps [k0, k0 + 64) of the run
+                        const bool ok = k0 + lane < kend;
+                        const int k = ok ? k0 + lane : kbeg;
+                        const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in degrid
+                        li[sl] = ok ? cell0 + row * kTile + (k - row * nc) : -1;
+                        K[sl] = load_tap(&tp[k]);
+                        k0 += 64;
                     }
                 }
-            });
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    const auto yx = bcast(y_l.x, ys[sl]), yy = bcast(y_l.y, ys[sl]);
+                    if (li[sl] >= 0) {
+                        const C z = tile[li[sl]];
+                        C o;
+                        o.x = z.x + (K[sl].x * yx + K[sl].y * yy);
+                        o.y = z.y + (K[sl].x * yy - K[sl].y * yx);
+                        tile[li[sl]] = o;
+                    }
+                }
+            }
         }
     }
     const uint32_t key = t.item_key[item];
@@ -505,9 +754,8 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     const Geom &g = c->g;
-    int64_t ncell = (int64_t)g.G * g.G * g.n_stacks;
     hipEvent_t ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_taper_pad<kFP64>, dim3(blocks(ncell, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_taper_pad<kFP64>, dim3(blocks((int64_t)g.G * g.G, 256)), dim3(256), 0, s,
                        (const R *)image, (C *)c->grids, d_centres, g);
     stage_end(c, kStTaperPad, ev, s);
     hipError_t e = hipGetLastError();
@@ -523,8 +771,14 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     ev = stage_begin(c, s);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        hipLaunchKernelGGL(k_degrid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
-                           (const C *)c->grids, (C *)c->scratch_dpart, ta);
+        // entries of a few tens of taps (many w-stacks) go four to a wavefront
+        if (pl.total_taps < kSmallEntryTaps * pl.n_entries) {
+            hipLaunchKernelGGL(k_degrid_small<kFP64>, dim3(nb), dim3(kThreads), 0, s,
+                               (const C *)c->taps, (const C *)c->grids, (C *)c->scratch_dpart, ta);
+        } else {
+            hipLaunchKernelGGL(k_degrid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
+                               (const C *)c->grids, (C *)c->scratch_dpart, ta);
+        }
     }
     hipLaunchKernelGGL(k_degrid_reduce<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s,
                        (const C *)c->scratch_dpart, pl.ent_off, (C *)vis, a);
@@ -551,8 +805,13 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
                        (C *)c->scratch_yw, a);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        hipLaunchKernelGGL(k_grid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
-                           (const C *)c->scratch_yw, (C *)c->grids, ta);
+        if (pl.total_taps < kSmallEntryTaps * pl.n_entries) {
+            hipLaunchKernelGGL(k_grid_small<kFP64>, dim3(nb), dim3(kThreads), 0, s,
+                               (const C *)c->taps, (const C *)c->scratch_yw, (C *)c->grids, ta);
+        } else {
+            hipLaunchKernelGGL(k_grid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
+                               (const C *)c->scratch_yw, (C *)c->grids, ta);
+        }
     }
     if (pl.n_mtiles > 0) {
         hipLaunchKernelGGL(k_reduce_tiles<kFP64>, dim3(pl.n_mtiles), dim3(256), 0, s, pl.mt_first,
