@@ -49,8 +49,8 @@ def parse():
                          "Poisson request stream from several imaging jobs")
     ap.add_argument("--serve-jobs", type=int, default=8)
     ap.add_argument("--serve-mmin", type=float, default=1e5)
-    ap.add_argument("--serve-mmax", type=float, default=2e6)
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-mmax", type=float, default=2e7)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.75)
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     return ap.parse_args()

@@ -80,6 +80,13 @@ wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
 
 size_t wsp::cplx_bytes(const wsp_ctx *c) { return c->p.precision == WSP_FP64 ? 16 : 8; }
 
+namespace {
+// the half-size transform buffer: K x N rows of G cells
+size_t half_bytes(const wsp_ctx *c) {
+    return (size_t)c->g.n_stacks * c->g.n * c->g.G * cplx_bytes(c);
+}
+}  // namespace
+
 hipEvent_t wsp::stage_begin(wsp_ctx *c, hipStream_t s) {
     if (!c->timer.enabled) return nullptr;
     hipEvent_t ev = nullptr;
@@ -219,26 +226,36 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     c->p = p;
     c->g = g;
     c->device = p.device;
-    if (hipfftCreate(&c->fft) != HIPFFT_SUCCESS) {
-        delete c;
-        return fail(WSP_EHIP, "hipfftCreate failed");
+    {
+        const hipfftType ty = p.precision == WSP_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C;
+        int len[1] = {g.G};
+        size_t wv = 0, wu = 0;
+        hipfftResult r = hipfftCreate(&c->fft_v);
+        if (r == HIPFFT_SUCCESS) {
+            c->fft_v_made = true;
+            hipfftSetAutoAllocation(c->fft_v, 0);
+            r = hipfftMakePlanMany(c->fft_v, 1, len, nullptr, 1, g.G, nullptr, 1, g.G, ty,
+                                   g.n_stacks * g.n, &wv);
+        }
+        if (r == HIPFFT_SUCCESS) r = hipfftCreate(&c->fft_u);
+        if (r == HIPFFT_SUCCESS) {
+            c->fft_u_made = true;
+            hipfftSetAutoAllocation(c->fft_u, 0);
+            r = hipfftMakePlanMany(c->fft_u, 1, len, nullptr, 1, g.G, nullptr, 1, g.G, ty,
+                                   g.n_stacks * g.G, &wu);
+        }
+        if (r != HIPFFT_SUCCESS) {
+            if (c->fft_v_made) hipfftDestroy(c->fft_v);
+            if (c->fft_u_made) hipfftDestroy(c->fft_u);
+            delete c;
+            return fail(WSP_EHIP, "hipfftMakePlanMany failed (" + std::to_string((int)r) + ")");
+        }
+        c->fft_work = wv > wu ? wv : wu;  // the two passes run in turn: one work area
     }
-    c->fft_made = true;
-    hipfftSetAutoAllocation(c->fft, 0);
-    int dims[2] = {g.G, g.G};
-    size_t work = 0;
-    hipfftResult r = hipfftMakePlanMany(c->fft, 2, dims, nullptr, 1, g.G * g.G, nullptr, 1,
-                                        g.G * g.G, p.precision == WSP_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C,
-                                        g.n_stacks, &work);
-    if (r != HIPFFT_SUCCESS) {
-        hipfftDestroy(c->fft);
-        delete c;
-        return fail(WSP_EHIP, "hipfftMakePlanMany failed (" + std::to_string((int)r) + ")");
-    }
-    c->fft_work = work;
     e = hipMalloc(&c->plan_centres, sizeof(double) * g.n_stacks);
     if (e != hipSuccess) {
-        hipfftDestroy(c->fft);
+        hipfftDestroy(c->fft_v);
+        hipfftDestroy(c->fft_u);
         delete c;
         return hip_fail(e, "hipMalloc centres");
     }
@@ -364,7 +381,7 @@ wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_by
     if (kernel_bytes) *kernel_bytes = (size_t)c->plan.total_taps * cb;
     if (grid_bytes) *grid_bytes = (size_t)c->g.G * c->g.G * c->g.n_stacks * cb;
     if (scratch_bytes)
-        *scratch_bytes = align256(c->fft_work) + align256((size_t)c->plan.m * cb) +
+        *scratch_bytes = align256(c->fft_work) + align256(half_bytes(c)) + align256((size_t)c->plan.m * cb) +
                          align256((size_t)c->plan.n_entries * cb) +
                          (size_t)c->plan.n_multi * kTile * kTile * cb;
     return WSP_OK;
@@ -382,9 +399,11 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
         return fail(WSP_ENOMEM_BINDING, "buffer smaller than wsp_footprint");
     if (((uintptr_t)kernels | (uintptr_t)grids | (uintptr_t)scratch) & 255u)
         return fail(WSP_EINVAL, "buffers must be 256-byte aligned");
-    if (c->fft_work > 0 && hipfftSetWorkArea(c->fft, scratch) != HIPFFT_SUCCESS)
+    if (c->fft_work > 0 && (hipfftSetWorkArea(c->fft_v, scratch) != HIPFFT_SUCCESS ||
+                            hipfftSetWorkArea(c->fft_u, scratch) != HIPFFT_SUCCESS))
         return fail(WSP_EHIP, "hipfftSetWorkArea failed");
-    c->scratch_yw = (char *)scratch + align256(c->fft_work);
+    c->scratch_half = (char *)scratch + align256(c->fft_work);
+    c->scratch_yw = (char *)c->scratch_half + align256(half_bytes(c));
     c->scratch_dpart = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
     c->scratch_part =
         (char *)c->scratch_dpart + align256((size_t)c->plan.n_entries * cplx_bytes(c));
@@ -532,7 +551,8 @@ void wsp_destroy(wsp_ctx *c) {
     free_sorted_plan(c->plan);
     free_caller(c->plan);
     hipFree(c->plan_centres);
-    if (c->fft_made) hipfftDestroy(c->fft);
+    if (c->fft_v_made) hipfftDestroy(c->fft_v);
+    if (c->fft_u_made) hipfftDestroy(c->fft_u);
     delete c;
 }
 

@@ -1,10 +1,12 @@
 // Operator application: y = Phi x (degrid) and x = Re Phi^dagger y (grid),
 // Eqs. (2)-(7).  Per stack k:
-//   degrid: S~_k and Z (k_taper_pad), F (hipFFT, batched over stacks),
-//           GC_k and W_k (k_degrid_tiles, k_degrid_reduce);
-//   grid:   W_k (k_prep_vis), GC_k^dagger (k_grid_tiles, k_reduce_tiles),
-//           F^dagger (hipFFT), Z^dagger, S~_k^dagger, Re and the sum over
-//           stacks (k_crop_untaper).
+//   degrid: S~_k and Z (k_taper_half), F (batched 1-D hipFFT passes with
+//           k_transpose_pad between them), GC_k and W_k (k_degrid_tiles or
+//           k_degrid_small, then k_degrid_reduce);
+//   grid:   W_k (k_prep_vis), GC_k^dagger (k_grid_tiles or k_grid_small,
+//           then k_reduce_tiles), F^dagger (hipFFT passes with
+//           k_transpose_crop), Z^dagger, S~_k^dagger, Re and the sum over
+//           stacks (k_crop_half).
 // Both sparse steps work on the tile work lists of the plan: each work item
 // is a run of (visibility, 64 x 64 grid tile) entries of one tile.
 #include <type_traits>
@@ -66,59 +68,145 @@ __device__ __forceinline__ int pixel_of(int V, const Geom &g) {
     return -1;
 }
 
-// S~_k and Z for all stacks: one thread per grid cell, looping over stacks.
+// F is computed in two passes of batched 1-D transforms of length G, with the
+// data transposed in between, so that neither pass touches the zero padding
+// that Z adds or the cells that Z^dagger discards:
+//   forward: H[k][i][V] = z_k[V][U(i)] for the N padded-image columns U(i)
+//            that hold pixels (k_taper_half), transform along V (rows of H),
+//            transpose into the grid with zero columns elsewhere
+//            (k_transpose_pad), transform along U (rows of the grid);
+//   inverse: transform along U, keep the N columns U(i) that the crop
+//            needs, transposed into H (k_transpose_crop), transform along V,
+//            crop, untaper and sum over stacks (k_crop_half).
+// Each transposing kernel stages a 64 x 64 tile in LDS so that its reads and
+// writes are both coalesced.
+constexpr int kT = 64;
+
+// column U of the padded image holding pixel column i (Z places pixel N/2 at 0)
+__device__ __forceinline__ int padded_of(int i, const Geom &g) {
+    int U = i - g.n / 2;
+    return U < 0 ? U + g.G : U;
+}
+
+// S~_k and Z for all stacks, written as H.  Block: (V tile, pixel-column tile).
 template <bool kFP64>
-__global__ void k_taper_pad(const typename Types<kFP64>::R *__restrict__ image,
-                            typename Types<kFP64>::C *grids, const double *__restrict__ centres,
-                            Geom g) {
+__global__ __launch_bounds__(256) void k_taper_half(const typename Types<kFP64>::R *__restrict__ image,
+                                                    typename Types<kFP64>::C *half,
+                                                    const double *__restrict__ centres, Geom g) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    const int64_t GG = (int64_t)g.G * g.G;
-    int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= GG) return;
-    int V = (int)(cell / g.G), U = (int)(cell - (int64_t)V * g.G);
-    int j = pixel_of(V, g), i = pixel_of(U, g);
-    C z;
-    z.x = 0;
-    z.y = 0;
-    if (j < 0 || i < 0) {
-        for (int k = 0; k < g.n_stacks; ++k) grids[k * GG + cell] = z;
-        return;
+    __shared__ R s_x[kT][kT + 1];  // [V offset][i offset]
+    const int V0 = blockIdx.x * kT, i0 = blockIdx.y * kT;
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int r = e / kT, cc = e % kT;  // along i: coalesced image reads
+        const int j = pixel_of(V0 + r, g), i = i0 + cc;
+        s_x[r][cc] = (j >= 0 && i < g.n) ? image[(int64_t)j * g.n + i] : (R)0;
     }
-    double amp, nm1;
-    pixel_factors(j, i, g, &amp, &nm1);
-    const R a = (R)((double)image[(int64_t)j * g.n + i] * amp);
-    for (int k = 0; k < g.n_stacks; ++k) {
-        R sn, cs;
-        rev_sincos<kFP64>(reduce_rev(-centres[k] * nm1), &sn, &cs);
-        z.x = a * cs;
-        z.y = a * sn;
-        grids[k * GG + cell] = z;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int cc = e / kT, r = e % kT;  // along V: coalesced writes of H
+        const int i = i0 + cc, V = V0 + r;
+        if (i >= g.n) continue;
+        const int j = pixel_of(V, g);
+        C z;
+        z.x = 0;
+        z.y = 0;
+        if (j < 0) {
+            for (int k = 0; k < g.n_stacks; ++k) half[((int64_t)k * g.n + i) * g.G + V] = z;
+            continue;
+        }
+        double amp, nm1;
+        pixel_factors(j, i, g, &amp, &nm1);
+        const R a = (R)((double)s_x[r][cc] * amp);
+        for (int k = 0; k < g.n_stacks; ++k) {
+            R sn, cs;
+            rev_sincos<kFP64>(reduce_rev(-centres[k] * nm1), &sn, &cs);
+            z.x = a * cs;
+            z.y = a * sn;
+            half[((int64_t)k * g.n + i) * g.G + V] = z;
+        }
     }
 }
 
-// Z^dagger, S~_k^dagger, Re and the sum over stacks: one thread per pixel.
-template <bool kFP64>
-__global__ void k_crop_untaper(const typename Types<kFP64>::C *__restrict__ grids,
-                               typename Types<kFP64>::R *image, const double *__restrict__ centres,
-                               Geom g) {
-    using R = typename Types<kFP64>::R;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)g.n * g.n) return;
-    int j = (int)(idx / g.n), i = (int)(idx - (int64_t)j * g.n);
-    int V = (j - g.n / 2 + g.G) % g.G, U = (i - g.n / 2 + g.G) % g.G;
-    const int64_t GG = (int64_t)g.G * g.G;
-    double amp, nm1;
-    pixel_factors(j, i, g, &amp, &nm1);
-    double acc = 0.0;
-    for (int k = 0; k < g.n_stacks; ++k) {
-        R sn, cs;
-        rev_sincos<kFP64>(reduce_rev(-centres[k] * nm1), &sn, &cs);
-        auto z = grids[k * GG + (int64_t)V * g.G + U];
-        // Re(z conj(s_k)) with s_k = amp e^{2 pi i rev}
-        acc += (double)(z.x * cs + z.y * sn);
+// grid[k][V][U] = H[k][i][V] where U = U(i), else 0.  Block: (V tile, U tile, stack).
+template <typename C>
+__global__ __launch_bounds__(256) void k_transpose_pad(const C *__restrict__ half, C *grids, Geom g) {
+    __shared__ C s_t[kT][kT + 1];  // [U offset][V offset]
+    const int V0 = blockIdx.x * kT, U0 = blockIdx.y * kT, k = blockIdx.z;
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int u = e / kT, v = e % kT;  // along V: coalesced reads of H
+        const int i = pixel_of(U0 + u, g);
+        C z;
+        z.x = 0;
+        z.y = 0;
+        if (i >= 0) z = half[((int64_t)k * g.n + i) * g.G + V0 + v];
+        s_t[u][v] = z;
     }
-    image[idx] = (R)(amp * acc);
+    __syncthreads();
+    C *dst = grids + (int64_t)k * g.G * g.G;
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int v = e / kT, u = e % kT;  // along U: coalesced grid writes
+        dst[(int64_t)(V0 + v) * g.G + U0 + u] = s_t[u][v];
+    }
+}
+
+// H[k][i][V] = grid[k][V][U(i)] for the N pixel columns.  Block: (V tile, i tile, stack).
+template <typename C>
+__global__ __launch_bounds__(256) void k_transpose_crop(const C *__restrict__ grids, C *half, Geom g) {
+    __shared__ C s_t[kT][kT + 1];  // [V offset][i offset]
+    const int V0 = blockIdx.x * kT, i0 = blockIdx.y * kT, k = blockIdx.z;
+    const C *src = grids + (int64_t)k * g.G * g.G;
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int v = e / kT, cc = e % kT;  // along i (U): coalesced grid reads
+        const int i = i0 + cc;
+        C z;
+        z.x = 0;
+        z.y = 0;
+        if (i < g.n) z = src[(int64_t)(V0 + v) * g.G + padded_of(i, g)];
+        s_t[v][cc] = z;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int cc = e / kT, v = e % kT;  // along V: coalesced writes of H
+        const int i = i0 + cc;
+        if (i < g.n) half[((int64_t)k * g.n + i) * g.G + V0 + v] = s_t[v][cc];
+    }
+}
+
+// Z^dagger, S~_k^dagger, Re and the sum over stacks from H.  Block: (j tile, i tile).
+template <bool kFP64>
+__global__ __launch_bounds__(256) void k_crop_half(const typename Types<kFP64>::C *__restrict__ half,
+                                                   typename Types<kFP64>::R *image,
+                                                   const double *__restrict__ centres, Geom g) {
+    using R = typename Types<kFP64>::R;
+    __shared__ R s_o[kT][kT + 1];  // [i offset][j offset]
+    const int j0 = blockIdx.x * kT, i0 = blockIdx.y * kT;
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int cc = e / kT, r = e % kT;  // along j (V): coalesced reads of H
+        const int i = i0 + cc, j = j0 + r;
+        R out = 0;
+        if (i < g.n && j < g.n) {
+            const int V = padded_of(j, g);
+            double amp, nm1;
+            pixel_factors(j, i, g, &amp, &nm1);
+            double acc = 0.0;
+            for (int k = 0; k < g.n_stacks; ++k) {
+                R sn, cs;
+                rev_sincos<kFP64>(reduce_rev(-centres[k] * nm1), &sn, &cs);
+                const auto z = half[((int64_t)k * g.n + i) * g.G + V];
+                // Re(z conj(s_k)) with s_k = amp e^{2 pi i rev}
+                acc += (double)(z.x * cs + z.y * sn);
+            }
+            out = (R)(amp * acc);
+        }
+        s_o[cc][r] = out;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int r = e / kT, cc = e % kT;  // along i: coalesced image writes
+        const int i = i0 + cc, j = j0 + r;
+        if (i < g.n && j < g.n) image[(int64_t)j * g.n + i] = s_o[cc][r];
+    }
 }
 
 template <typename C>
@@ -735,17 +823,39 @@ ApplyArgs make_args(const wsp_ctx *c) {
     return a;
 }
 
-hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
-    if (hipfftSetStream(c->fft, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
-    hipfftResult r;
-    if (c->p.precision == WSP_FP64) {
-        r = hipfftExecZ2Z(c->fft, (hipfftDoubleComplex *)c->grids, (hipfftDoubleComplex *)c->grids,
-                          forward ? HIPFFT_FORWARD : HIPFFT_BACKWARD);
+template <typename C>
+hipfftResult fft_pass(hipfftHandle plan, C *data, int dir, hipStream_t s) {
+    hipfftResult r = hipfftSetStream(plan, s);
+    if (r != HIPFFT_SUCCESS) return r;
+    if constexpr (sizeof(C) == 16) {
+        return hipfftExecZ2Z(plan, (hipfftDoubleComplex *)data, (hipfftDoubleComplex *)data, dir);
     } else {
-        r = hipfftExecC2C(c->fft, (hipfftComplex *)c->grids, (hipfftComplex *)c->grids,
-                          forward ? HIPFFT_FORWARD : HIPFFT_BACKWARD);
+        return hipfftExecC2C(plan, (hipfftComplex *)data, (hipfftComplex *)data, dir);
     }
-    return r == HIPFFT_SUCCESS ? hipSuccess : hipErrorUnknown;
+}
+
+// F (forward, from H to the grids) or F^dagger (backward, from the grids to H),
+// both unnormalised.
+template <typename C>
+hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
+    const Geom &g = c->g;
+    C *grids = (C *)c->grids, *half = (C *)c->scratch_half;
+    const dim3 tgrid((unsigned)(g.G / kT), (unsigned)((g.n + kT - 1) / kT), (unsigned)g.n_stacks);
+    if (forward) {
+        if (fft_pass(c->fft_v, half, HIPFFT_FORWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+        hipLaunchKernelGGL(k_transpose_pad<C>, dim3(g.G / kT, g.G / kT, g.n_stacks), dim3(256), 0, s,
+                           (const C *)half, grids, g);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (fft_pass(c->fft_u, grids, HIPFFT_FORWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+    } else {
+        if (fft_pass(c->fft_u, grids, HIPFFT_BACKWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+        hipLaunchKernelGGL(k_transpose_crop<C>, tgrid, dim3(256), 0, s, (const C *)grids, half, g);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (fft_pass(c->fft_v, half, HIPFFT_BACKWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+    }
+    return hipSuccess;
 }
 
 template <bool kFP64>
@@ -755,13 +865,13 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     using C = typename Types<kFP64>::C;
     const Geom &g = c->g;
     hipEvent_t ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_taper_pad<kFP64>, dim3(blocks((int64_t)g.G * g.G, 256)), dim3(256), 0, s,
-                       (const R *)image, (C *)c->grids, d_centres, g);
+    hipLaunchKernelGGL(k_taper_half<kFP64>, dim3(g.G / kT, (g.n + kT - 1) / kT), dim3(256), 0, s,
+                       (const R *)image, (C *)c->scratch_half, d_centres, g);
     stage_end(c, kStTaperPad, ev, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ev = stage_begin(c, s);
-    e = fft_exec(c, true, s);
+    e = fft_exec<C>(c, true, s);
     stage_end(c, kStFftForward, ev, s);
     if (e != hipSuccess) return e;
     ApplyArgs a = make_args(c);
@@ -821,12 +931,12 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ev = stage_begin(c, s);
-    e = fft_exec(c, false, s);
+    e = fft_exec<C>(c, false, s);
     stage_end(c, kStFftInverse, ev, s);
     if (e != hipSuccess) return e;
     ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_crop_untaper<kFP64>, dim3(blocks((int64_t)g.n * g.n, 256)), dim3(256), 0,
-                       s, (const C *)c->grids, (R *)image, d_centres, g);
+    hipLaunchKernelGGL(k_crop_half<kFP64>, dim3((g.n + kT - 1) / kT, (g.n + kT - 1) / kT), dim3(256),
+                       0, s, (const C *)c->scratch_half, (R *)image, d_centres, g);
     stage_end(c, kStCropUntaper, ev, s);
     return hipGetLastError();
 }

@@ -120,8 +120,11 @@ struct wsp_ctx {
     wsp_params p{};
     wsp::Geom g{};
     int device = 0;
-    hipfftHandle fft = 0;
-    bool fft_made = false;
+    // F as two passes of batched 1-D transforms of length G: along V over the
+    // K x N rows of the half-size buffer (columns of the padded image that hold
+    // pixels), and along U over the K x G rows of the grids
+    hipfftHandle fft_v = 0, fft_u = 0;
+    bool fft_v_made = false, fft_u_made = false;
     size_t fft_work = 0;
     wsp::Plan plan;
     bool planned = false;
@@ -134,6 +137,7 @@ struct wsp_ctx {
     size_t grid_bytes = 0;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    void *scratch_half = nullptr;   // [K][N][G] half-size transform buffer (inside scratch)
     void *scratch_yw = nullptr;     // weighted adjoint input, sorted order (inside scratch)
     void *scratch_part = nullptr;   // partial tiles of shared grid tiles (inside scratch)
     void *scratch_dpart = nullptr;  // degrid partial sums, one per tile entry (inside scratch)
