@@ -290,6 +290,10 @@ constexpr int kChunk = 256;           // degrid: entries whose metadata is stage
 constexpr int kGChunk = 128;          // grid: the same (smaller: the block also holds y per entry)
 constexpr int kBand = kTile / kWaves; // grid: tile rows owned by each wavefront
 constexpr int64_t kSmallEntryTaps = 160;  // mean taps per entry below which k_degrid_small / k_grid_small run
+// grid: blocks per work item, each owning kTile / split rows of the tile (more,
+// smaller blocks keep more wavefronts resident when bands finish unevenly)
+constexpr int kGridSplit = 2;
+constexpr int kGridSplitSmall = 4;
 
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef double v2d_t __attribute__((ext_vector_type(2)));
@@ -532,34 +536,38 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
     vis[a.perm[p]] = y;
 }
 
-// GC_k^dagger (grid), one block per work item, no atomics: the item's 64 x 64
-// tile accumulates in LDS, and wavefront w owns tile rows [8 w, 8 w + 8): no
-// other wavefront touches them.  Every wavefront scans all entries of the
+// GC_k^dagger (grid), kH blocks per work item, no atomics: block b of an item
+// accumulates rows [64 b / kH, 64 (b + 1) / kH) of the item's 64 x 64 tile in
+// LDS, and each of its wavefronts owns 8 of those rows: no other wavefront
+// touches them.  Every wavefront scans all entries of the
 // item (64 per ballot); for each entry with rows in its band it streams the
 // taps of those rows (a contiguous run of the row-major sub-block), lanes on
 // consecutive taps, and adds conj(K) yw to the owned cells.  The cells of one entry are distinct
 // and a wavefront's LDS accesses complete in order, so plain read-modify-
 // write is exact.  The tile is then stored into the grid (the tile's only
 // item) or into a partial-tile slot that k_reduce_tiles sums in item order.
-template <bool kFP64>
-__global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
+template <bool kFP64, int kH>
+__global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
                                                          const typename Types<kFP64>::C *__restrict__ yw,
                                                          typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
-    __shared__ C tile[kTile * kTile];
+    constexpr int kRows = kTile / kH;  // tile rows of this block
+    __shared__ C tile[kRows * kTile];
     __shared__ int4 s_ent[kGChunk];
     __shared__ int64_t s_off[kGChunk];
     __shared__ int s_jp[kGChunk];
     __shared__ C s_y[kGChunk];
-    static_assert(kGChunk <= kThreads, "one thread stages one entry");
-    const int item = xcd_item(blockIdx.x, t.n_items);
+    static_assert(kGChunk <= kThreads / kH, "one thread stages one entry");
+    const int part = blockIdx.x % kH;
+    const int item = xcd_item(blockIdx.x / kH, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
-    const int band0 = (threadIdx.x >> 6) * kBand;
+    const int lrow0 = (threadIdx.x >> 6) * kBand;  // band start in the LDS tile
+    const int band0 = part * kRows + lrow0;       // and in the grid tile
     C zero;
     zero.x = 0;
     zero.y = 0;
-    for (int i = lane; i < kBand * kTile; i += 64) tile[band0 * kTile + i] = zero;
+    for (int i = lane; i < kBand * kTile; i += 64) tile[lrow0 * kTile + i] = zero;
     const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
     for (int base = s_beg; base < s_end; base += kGChunk) {
         const int n = (s_end - base < kGChunk) ? s_end - base : kGChunk;
@@ -608,7 +616,7 @@ __global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_tiles(const ty
                 const C *tp = taps + off + blocked_entry_offset(r0, nr, c0, jp);
                 const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
                 const float inv_nc = 1.0f / (float)nc;
-                const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
+                const int cell0 = (ly0 - part * kRows) * kTile + lx0;  // LDS cell of sub-block tap 0
                 for_batches(kbeg, kend, [&](int k0, auto ucount) {
                     constexpr int U = decltype(ucount)::value;
                     C K[U], z[U];
@@ -649,7 +657,7 @@ __global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_tiles(const ty
     }
     // the band was written by this wavefront only: no barrier needed
 #pragma unroll
-    for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(band0 + r) * kTile + lane];
+    for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(lrow0 + r) * kTile + lane];
 }
 
 // Grid for work lists of small entries: band ownership, ballot scan and
@@ -659,24 +667,27 @@ __global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_tiles(const ty
 // runs) are issued together; then the slots are added into the tile one
 // after the other, in entry order (two entries may share cells).
 constexpr int kSlots = 8;
-template <bool kFP64>
-__global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_small(const typename Types<kFP64>::C *__restrict__ taps,
+template <bool kFP64, int kH>
+__global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(const typename Types<kFP64>::C *__restrict__ taps,
                                                                         const typename Types<kFP64>::C *__restrict__ yw,
                                                                         typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
-    __shared__ C tile[kTile * kTile];
+    constexpr int kRows = kTile / kH;  // tile rows of this block
+    __shared__ C tile[kRows * kTile];
     __shared__ int4 s_ent[kGChunk];
     __shared__ int64_t s_off[kGChunk];
     __shared__ int s_jp[kGChunk];
     __shared__ C s_y[kGChunk];
-    const int item = xcd_item(blockIdx.x, t.n_items);
+    const int part = blockIdx.x % kH;
+    const int item = xcd_item(blockIdx.x / kH, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
-    const int band0 = (threadIdx.x >> 6) * kBand;
+    const int lrow0 = (threadIdx.x >> 6) * kBand;  // band start in the LDS tile
+    const int band0 = part * kRows + lrow0;       // and in the grid tile
     C zero;
     zero.x = 0;
     zero.y = 0;
-    for (int i = lane; i < kBand * kTile; i += 64) tile[band0 * kTile + i] = zero;
+    for (int i = lane; i < kBand * kTile; i += 64) tile[lrow0 * kTile + i] = zero;
     const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
     for (int base = s_beg; base < s_end; base += kGChunk) {
         const int n = (s_end - base < kGChunk) ? s_end - base : kGChunk;
@@ -732,7 +743,7 @@ __global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_small(const ty
                         kend = (hi - ly0) * nc;
                         k0 = kbeg;
                         inv_nc = 1.0f / (float)nc;
-                        cell0 = ly0 * kTile + ((ez >> 16) & 255);
+                        cell0 = (ly0 - part * kRows) * kTile + ((ez >> 16) & 255);
                     }
                     K[sl] = zero;
                     ys[sl] = yl;
@@ -771,7 +782,7 @@ __global__ __launch_bounds__(kThreads, kFP64 ? 4 : 8) void k_grid_small(const ty
     }
     // the band was written by this wavefront only: no barrier needed
 #pragma unroll
-    for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(band0 + r) * kTile + lane];
+    for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(lrow0 + r) * kTile + lane];
 }
 
 // Sum the partial tiles of each tile shared by several items, in item order
@@ -916,10 +927,12 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
         if (pl.total_taps < kSmallEntryTaps * pl.n_entries) {
-            hipLaunchKernelGGL(k_grid_small<kFP64>, dim3(nb), dim3(kThreads), 0, s,
-                               (const C *)c->taps, (const C *)c->scratch_yw, (C *)c->grids, ta);
+            hipLaunchKernelGGL((k_grid_small<kFP64, kGridSplitSmall>), dim3(kGridSplitSmall * nb),
+                               dim3(kThreads / kGridSplitSmall), 0, s, (const C *)c->taps,
+                               (const C *)c->scratch_yw, (C *)c->grids, ta);
         } else {
-            hipLaunchKernelGGL(k_grid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
+            hipLaunchKernelGGL((k_grid_tiles<kFP64, kGridSplit>), dim3(kGridSplit * nb),
+                               dim3(kThreads / kGridSplit), 0, s, (const C *)c->taps,
                                (const C *)c->scratch_yw, (C *)c->grids, ta);
         }
     }
