@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     constexpr int kPer = 64 / kGroup;  // entries per wavefront pass
-    constexpr int kU = 2;              // loads per lane in flight
+    constexpr int kU = 4;              // loads per lane in flight
     __shared__ C tile[kTile * kTile];
     __shared__ int4 s_ent[kChunk];
     __shared__ int s_idx[kChunk];
