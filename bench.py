@@ -56,8 +56,10 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mwa_1024_single_stack.json")
-TRAFFIC_SOURCES = ("paper_1903_06555_amd/csrc/apply.hip", "paper_1903_06555_amd/csrc/wsp_internal.h")
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+TRAFFIC_SOURCES = ("paper_1903_06555_amd/csrc/apply.hip", "paper_1903_06555_amd/csrc/wsp_internal.h",
+                   "paper_1903_06555_amd/csrc/plan.hip")
 
 
 def source_digest() -> str:
@@ -74,7 +76,7 @@ def measured_traffic(kernel: str, workload: str, m: int):
     readings (calibrated on a plain copy), or None if they were taken on other
     kernel sources or another workload."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(workload)) as fh:
             rec = json.load(fh)
     except OSError:
         return None

@@ -253,15 +253,13 @@ __global__ void k_prep_vis(const typename Types<kFP64>::C *__restrict__ vis,
 }
 
 struct TileArgs {
-    const int4 *ent;
-    const int32_t *ent_sorted;
+    const int4 *wrec;           // entry records in work-list order
+    const int32_t *ent_sorted;  // entry indices in work-list order
     const int32_t *item_start;
     const uint32_t *item_key;
     const uint8_t *item_sole;
     const int32_t *item_slot;
     void *partial;
-    const int32_t *jp;
-    const int64_t *tap_off;
     int n_items;
     int tile_bits;
     int G;
@@ -355,10 +353,9 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     __shared__ C tile[kTile * kTile];
-    __shared__ int4 s_ent[kChunk];
+    __shared__ int s_geo[kChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int s_idx[kChunk];
     __shared__ int64_t s_off[kChunk];
-    __shared__ int s_jp[kChunk];
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     {
@@ -373,20 +370,17 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
         const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
         __syncthreads();  // tile staged / previous chunk consumed
         for (int q = threadIdx.x; q < n; q += kThreads) {
-            const int e = t.ent_sorted[base + q];
-            const int4 en = t.ent[e];
-            s_ent[q] = en;
-            s_idx[q] = e;
-            s_off[q] = t.tap_off[en.x];
-            s_jp[q] = t.jp[en.x];
+            const int4 rec = t.wrec[base + q];
+            s_geo[q] = rec.z;
+            s_idx[q] = t.ent_sorted[base + q];
+            s_off[q] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
         }
         __syncthreads();
         for (int j = wid; j < n; j += kWaves) {
-            const int4 en = s_ent[j];
-            const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
-            const int nc = en.z & 255, nr = (en.z >> 8) & 255;
-            const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
-            const C *tp = taps + s_off[j] + blocked_entry_offset(r0, nr, c0, s_jp[j]);
+            const int geo = s_geo[j];
+            const int nc = geo & 255, nr = (geo >> 8) & 255;
+            const int lx0 = (geo >> 16) & 255, ly0 = (geo >> 24) & 255;
+            const C *tp = taps + s_off[j];
             const float inv_nc = 1.0f / (float)nc;
             const int ntap = nr * nc;
             const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
@@ -439,10 +433,9 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
     constexpr int kPer = 64 / kGroup;  // entries per wavefront pass
     constexpr int kU = 4;              // loads per lane in flight
     __shared__ C tile[kTile * kTile];
-    __shared__ int4 s_ent[kChunk];
+    __shared__ int s_geo[kChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int s_idx[kChunk];
     __shared__ int64_t s_off[kChunk];
-    __shared__ int s_jp[kChunk];
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     {
@@ -458,22 +451,19 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
         const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
         __syncthreads();  // tile staged / previous chunk consumed
         for (int q = threadIdx.x; q < n; q += kThreads) {
-            const int e = t.ent_sorted[base + q];
-            const int4 en = t.ent[e];
-            s_ent[q] = en;
-            s_idx[q] = e;
-            s_off[q] = t.tap_off[en.x];
-            s_jp[q] = t.jp[en.x];
+            const int4 rec = t.wrec[base + q];
+            s_geo[q] = rec.z;
+            s_idx[q] = t.ent_sorted[base + q];
+            s_off[q] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
         }
         __syncthreads();
         for (int j0 = wid * kPer; j0 < n; j0 += kWaves * kPer) {
             const int j = j0 + grp;
             const bool valid = j < n;
-            const int4 en = s_ent[valid ? j : j0];
-            const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
-            const int nc = en.z & 255, nr = (en.z >> 8) & 255;
-            const int lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
-            const C *tp = taps + s_off[valid ? j : j0] + blocked_entry_offset(r0, nr, c0, s_jp[valid ? j : j0]);
+            const int geo = s_geo[valid ? j : j0];
+            const int nc = geo & 255, nr = (geo >> 8) & 255;
+            const int lx0 = (geo >> 16) & 255, ly0 = (geo >> 24) & 255;
+            const C *tp = taps + s_off[valid ? j : j0];
             const float inv_nc = 1.0f / (float)nc;
             const int ntap = valid ? nr * nc : 0;
             const int cell0 = ly0 * kTile + lx0;
@@ -553,9 +543,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
     using C = typename Types<kFP64>::C;
     constexpr int kRows = kTile / kH;  // tile rows of this block
     __shared__ C tile[kRows * kTile];
-    __shared__ int4 s_ent[kGChunk];
+    __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int64_t s_off[kGChunk];
-    __shared__ int s_jp[kGChunk];
     __shared__ C s_y[kGChunk];
     static_assert(kGChunk <= kThreads / kH, "one thread stages one entry");
     const int part = blockIdx.x % kH;
@@ -573,11 +562,10 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
         const int n = (s_end - base < kGChunk) ? s_end - base : kGChunk;
         __syncthreads();  // previous chunk consumed
         if ((int)threadIdx.x < n) {
-            const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
-            s_ent[threadIdx.x] = en;
-            s_off[threadIdx.x] = t.tap_off[en.x];
-            s_jp[threadIdx.x] = t.jp[en.x];
-            s_y[threadIdx.x] = yw[en.x];
+            const int4 rec = t.wrec[base + threadIdx.x];
+            s_geo[threadIdx.x] = rec.z;
+            s_off[threadIdx.x] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            s_y[threadIdx.x] = yw[rec.w];
         }
         __syncthreads();
         // 64 entries at a time: lane l holds entry j0 + l; a ballot marks the
@@ -585,35 +573,30 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
         // with readlane (no memory round trip per entry).
         for (int j0 = 0; j0 < n; j0 += 64) {
             const int jl = j0 + lane;
-            int4 en_l = make_int4(0, 0, 0, 0);
+            int geo_l = 0;
             int64_t off_l = 0;
-            int jp_l = 0;
             C y_l = zero;
             if (jl < n) {
-                en_l = s_ent[jl];
+                geo_l = s_geo[jl];
                 off_l = s_off[jl];
-                jp_l = s_jp[jl];
                 y_l = s_y[jl];
             }
-            const int nr_l = (en_l.z >> 8) & 255, ly0_l = (en_l.z >> 24) & 255;
+            const int nr_l = (geo_l >> 8) & 255, ly0_l = (geo_l >> 24) & 255;
             uint64_t hits = __ballot(jl < n && ly0_l < band0 + kBand && ly0_l + nr_l > band0);
             while (hits) {
                 const int l = __builtin_ctzll(hits);
                 hits &= hits - 1;
-                const int ey = __builtin_amdgcn_readlane(en_l.y, l);
-                const int ez = __builtin_amdgcn_readlane(en_l.z, l);
+                const int ez = __builtin_amdgcn_readlane(geo_l, l);
                 const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
                                     (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
-                const int jp = __builtin_amdgcn_readlane(jp_l, l);
                 C y;
                 y.x = bcast(y_l.x, l);
                 y.y = bcast(y_l.y, l);
                 const int nr = (ez >> 8) & 255, ly0 = (ez >> 24) & 255;
                 const int lo = ly0 > band0 ? ly0 : band0;
                 const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
-                const int c0 = ey & 0xFFFF, r0 = (ey >> 16) & 0xFFFF;
                 const int nc = ez & 255, lx0 = (ez >> 16) & 255;
-                const C *tp = taps + off + blocked_entry_offset(r0, nr, c0, jp);
+                const C *tp = taps + off;
                 const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
                 const float inv_nc = 1.0f / (float)nc;
                 const int cell0 = (ly0 - part * kRows) * kTile + lx0;  // LDS cell of sub-block tap 0
@@ -674,9 +657,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
     using C = typename Types<kFP64>::C;
     constexpr int kRows = kTile / kH;  // tile rows of this block
     __shared__ C tile[kRows * kTile];
-    __shared__ int4 s_ent[kGChunk];
+    __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int64_t s_off[kGChunk];
-    __shared__ int s_jp[kGChunk];
     __shared__ C s_y[kGChunk];
     const int part = blockIdx.x % kH;
     const int item = xcd_item(blockIdx.x / kH, t.n_items);
@@ -693,26 +675,23 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
         const int n = (s_end - base < kGChunk) ? s_end - base : kGChunk;
         __syncthreads();  // previous chunk consumed
         if ((int)threadIdx.x < n) {
-            const int4 en = t.ent[t.ent_sorted[base + threadIdx.x]];
-            s_ent[threadIdx.x] = en;
-            s_off[threadIdx.x] = t.tap_off[en.x];
-            s_jp[threadIdx.x] = t.jp[en.x];
-            s_y[threadIdx.x] = yw[en.x];
+            const int4 rec = t.wrec[base + threadIdx.x];
+            s_geo[threadIdx.x] = rec.z;
+            s_off[threadIdx.x] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            s_y[threadIdx.x] = yw[rec.w];
         }
         __syncthreads();
         for (int j0 = 0; j0 < n; j0 += 64) {
             const int jl = j0 + lane;
-            int4 en_l = make_int4(0, 0, 0, 0);
+            int geo_l = 0;
             int64_t off_l = 0;
-            int jp_l = 0;
             C y_l = zero;
             if (jl < n) {
-                en_l = s_ent[jl];
+                geo_l = s_geo[jl];
                 off_l = s_off[jl];
-                jp_l = s_jp[jl];
                 y_l = s_y[jl];
             }
-            const int nr_l = (en_l.z >> 8) & 255, ly0_l = (en_l.z >> 24) & 255;
+            const int nr_l = (geo_l >> 8) & 255, ly0_l = (geo_l >> 24) & 255;
             uint64_t hits = __ballot(jl < n && ly0_l < band0 + kBand && ly0_l + nr_l > band0);
             // current run (uniform): taps [k0, kend) of the entry's rows in the
             // band; the entry's y sits in lane yl of y_l
@@ -728,17 +707,15 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                     if (k0 >= kend && hits) {  // next entry with rows in the band
                         const int l = __builtin_ctzll(hits);
                         hits &= hits - 1;
-                        const int ey = __builtin_amdgcn_readlane(en_l.y, l);
-                        const int ez = __builtin_amdgcn_readlane(en_l.z, l);
+                        const int ez = __builtin_amdgcn_readlane(geo_l, l);
                         const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
                                             (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
-                        const int jp = __builtin_amdgcn_readlane(jp_l, l);
                         yl = l;
                         const int nr = (ez >> 8) & 255, ly0 = (ez >> 24) & 255;
                         const int lo = ly0 > band0 ? ly0 : band0;
                         const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
                         nc = ez & 255;
-                        tp = taps + off + blocked_entry_offset((ey >> 16) & 0xFFFF, nr, ey & 0xFFFF, jp);
+                        tp = taps + off;
                         kbeg = (lo - ly0) * nc;
                         kend = (hi - ly0) * nc;
                         k0 = kbeg;
@@ -887,8 +864,8 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     if (e != hipSuccess) return e;
     ApplyArgs a = make_args(c);
     const Plan &pl = c->plan;
-    TileArgs ta{pl.ent,      pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole,
-                pl.item_slot, c->scratch_part, pl.jp, pl.tap_off, pl.n_items, pl.tile_bits, g.G};
+    TileArgs ta{pl.wrec,      pl.ent_sorted,   pl.item_start, pl.item_key, pl.item_sole,
+                pl.item_slot, c->scratch_part, pl.n_items,    pl.tile_bits, g.G};
     ev = stage_begin(c, s);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
@@ -919,8 +896,8 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     stage_end(c, kStZero, ev, s);
     ApplyArgs a = make_args(c);
     const Plan &pl = c->plan;
-    TileArgs ta{pl.ent,      pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole,
-                pl.item_slot, c->scratch_part, pl.jp, pl.tap_off, pl.n_items, pl.tile_bits, g.G};
+    TileArgs ta{pl.wrec,      pl.ent_sorted,   pl.item_start, pl.item_key, pl.item_sole,
+                pl.item_slot, c->scratch_part, pl.n_items,    pl.tile_bits, g.G};
     ev = stage_begin(c, s);
     hipLaunchKernelGGL(k_prep_vis<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)vis,
                        (C *)c->scratch_yw, a);

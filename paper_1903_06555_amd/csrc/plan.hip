@@ -295,6 +295,19 @@ __global__ void k_entry_fill(const int32_t *__restrict__ jp, const int32_t *__re
     }
 }
 
+// Per-entry records in work-list order, so that the tile kernels read their
+// entries' metadata sequentially rather than through three gathers.
+__global__ void k_entry_records(const int32_t *__restrict__ idx_sorted, const int4 *__restrict__ ent,
+                                const int64_t *__restrict__ tap_off, const int32_t *__restrict__ jp,
+                                int64_t E, int4 *wrec) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= E) return;
+    const int4 en = ent[idx_sorted[s]];
+    const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF, nr = (en.z >> 8) & 255;
+    const int64_t first = tap_off[en.x] + blocked_entry_offset(r0, nr, c0, jp[en.x]);
+    wrec[s] = make_int4((int)(uint32_t)first, (int)(first >> 32), en.z, en.x);
+}
+
 __global__ void k_entry_work(const uint32_t *__restrict__ keys_sorted,
                              const int32_t *__restrict__ idx_sorted, const int4 *__restrict__ ent,
                              int64_t E, int64_t *work, uint8_t *head) {
@@ -404,7 +417,7 @@ void free_sorted_plan(Plan &pl) {
     void *ptrs[] = {pl.perm,   pl.ux,      pl.vx,         pl.weff,     pl.wt,
                     pl.jp,     pl.u0w,     pl.v0w,        pl.stack,    pl.sflag,
                     pl.tap_off, pl.border, pl.stats,      pl.ent,      pl.ent_off,
-                    pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole};
+                    pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole, pl.wrec};
     for (void *q : ptrs) hipFree(q);
     pl.perm = nullptr;
     pl.ux = pl.vx = pl.weff = pl.wt = nullptr;
@@ -415,6 +428,7 @@ void free_sorted_plan(Plan &pl) {
     pl.ent = nullptr;
     pl.ent_off = nullptr;
     pl.ent_sorted = pl.item_start = nullptr;
+    pl.wrec = nullptr;
     pl.item_key = nullptr;
     pl.item_sole = nullptr;
     pl.n_entries = 0;
@@ -502,6 +516,9 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     WSP_ESTEP(dalloc(&ihead, E));
     hipLaunchKernelGGL(k_entry_work, dim3(grid1d(E, 256)), dim3(256), 0, s, keys_sorted,
                        pl.ent_sorted, pl.ent, E, work, head);
+    WSP_ESTEP(dalloc(&pl.wrec, E));
+    hipLaunchKernelGGL(k_entry_records, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent_sorted, pl.ent,
+                       pl.tap_off, pl.jp, E, pl.wrec);
     need = 0;
     WSP_ESTEP(hipcub::DeviceScan::InclusiveSum(nullptr, need, work, incl, (int)E, s));
     WSP_ESTEP(scratch(need));

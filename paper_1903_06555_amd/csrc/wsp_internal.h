@@ -92,6 +92,9 @@ struct Plan {
     int4 *ent = nullptr;          // [n_entries] {vis, c0 | r0 << 16, nc | nr << 8 | lx0 << 16 | ly0 << 24, key}
     int64_t *ent_off = nullptr;   // [m + 1] first entry of each sorted visibility
     int32_t *ent_sorted = nullptr;// [n_entries] entry indices in (stack, tile) order
+    int4 *wrec = nullptr;         // [n_entries] in (stack, tile) order: {index of the entry's first
+                                  // tap in the tap array (low, high 32 bits), nc | nr << 8 |
+                                  // lx0 << 16 | ly0 << 24, visibility}
     int32_t *item_start = nullptr;// [n_items + 1] ranges of ent_sorted
     uint32_t *item_key = nullptr; // [n_items] (stack, tile) key of each item
     uint8_t *item_sole = nullptr; // [n_items] 1 if the item is its tile's only item
