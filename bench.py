@@ -243,6 +243,23 @@ def serving(args):
     vis = sum(srv.jobs[r.job_id].uvw.shape[0] for r in reqs)
     unbatched_s = sum(t_alone[(r.job_id, r.kind)] for r in reqs)
     lat = srv.latency_percentiles()
+    for r in reqs:
+        r.result = None
+    # saturated: the same requests all queued at once (closed loop); requests of
+    # different jobs run concurrently, each job's in order
+    srv.done = []
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    sat = []
+    for name, kind in plan:
+        x, y = inputs[name]
+        sat.append(srv.submit(name, kind, x if kind == "forward" else y))
+    srv.drain()
+    torch.cuda.synchronize()
+    wall_sat = time.perf_counter() - start
+    for r in sat:
+        r.result = None
+    log(f"saturated: {len(sat)} requests in {wall_sat:.2f} s")
     for name in list(srv.jobs):
         if srv.jobs[name].op is not None:
             srv.retire_job(name)
@@ -268,6 +285,7 @@ def serving(args):
         "mode": "serving", "requests": len(reqs), "wall_s": wall,
         "value": vis / wall / 1e6, "unit": "Mvis/s",
         "latency_ms": lat, "offered_load": args.serve_load,
+        "saturated_mvis_per_s": vis / wall_sat / 1e6,
         "unbatched_mvis_per_s": vis / unbatched_s / 1e6,
         "unbatched_fp64_mvis_per_s": vis / unbatched64_s / 1e6,
         "jobs": [{"name": a, "n": b, "m": c, "stacks": d} for a, b, c, d, _ in live],

@@ -192,7 +192,7 @@ def main():
     tmin = mp.mpf(1) / 10 ** 6
     fP = lambda t: p0q0(8 / mp.sqrt(t))[0]
     fR = lambda t: p0q0(8 / mp.sqrt(t))[1] * (8 / mp.sqrt(t)) / 8
-    deg_l = 5
+    deg_l = 3
     cP = fit_in_t(fP, deg_l, tmin, mp.mpf(1))
     cR = fit_in_t(fR, deg_l, tmin, mp.mpf(1))
     eP = max_err(fP, lambda t: horner(cP, t), tmin, 1)
