@@ -233,6 +233,11 @@ def main():
     lines.append(f"#define WSP_SC64_N {deg_sc64 + 1}")
     lines.append("static __constant__ double wsp_sin_c64[] = {" + ", ".join(mp.nstr(v, 20) for v in cS64) + "};")
     lines.append("static __constant__ double wsp_cos_c64[] = {" + ", ".join(mp.nstr(v, 20) for v in cC64) + "};")
+    # Lagrange interpolation on the 10 equispaced nodes 0..9:
+    # l_k(u) = c_k prod_{j != k} (u - j), c_k = (-1)^(9 - k) / (k! (9 - k)!)
+    lines.append("/* 10-point equispaced Lagrange basis: c_k = (-1)^(9-k) / (k! (9-k)!) */")
+    lines.append("static __constant__ double wsp_lagrange10_c[10] = {" + ", ".join(
+        repr(float(mp.mpf((-1) ** (9 - k)) / (mp.factorial(k) * mp.factorial(9 - k)))) for k in range(10)) + "};")
     # reciprocals 1 / ((k + 1) (k + 2)) for the power series of I1(z) / z in z^2 / 4
     lines.append("/* 1 / ((k + 1) (k + 2)), k = 0..127: ratio of successive terms of sum_k y^k / (k! (k+1)!) */")
     lines.append("#define WSP_SERIES_N 128")
