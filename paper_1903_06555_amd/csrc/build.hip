@@ -141,7 +141,10 @@ __device__ float eval_panel_probes(double a, double b, double weff, double qstep
         double wk = wsp_gk_wk[n], wg = wsp_gk_wg[n];
 #pragma unroll
         for (int j = 0; j < kProbes; ++j) {
-            double J = j0(kTwoPi * r * (qstep * j));
+            const double q = qstep * j;
+            const double x = kTwoPi * (r * q);
+            // 8 / x and sqrt(2 / (pi x)) for the Hankel branch (x >= 8 there)
+            const double J = x < 8.0 ? j0_small(x) : j0_fp64(r, q, 8.0 / x, sqrt(0.6366197723675814 / x));
             double tr = are * J, ti = aim * J;
             kr[j] = fma(wk, tr, kr[j]);
             ki[j] = fma(wk, ti, ki[j]);
