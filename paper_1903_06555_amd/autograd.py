@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import torch
 
+from .imaging import power_norm2  # noqa: F401  (||Phi||^2 for step sizes)
 from .wsp import Operator
 
 
@@ -26,16 +27,3 @@ class WStackDegrid(torch.autograd.Function):
 
 def degrid(image: torch.Tensor, op: Operator) -> torch.Tensor:
     return WStackDegrid.apply(image, op)
-
-
-def power_norm2(op: Operator, n_iter: int = 30, seed: int = 0) -> float:
-    """||Phi||^2 (largest eigenvalue of Re Phi^dagger Phi) by the power method."""
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    x = torch.randn(op.n, op.n, generator=g, dtype=torch.float64).to(op.device, op.real_dtype)
-    x /= torch.linalg.vector_norm(x)
-    lam = 0.0
-    for _ in range(n_iter):
-        z = op.grid(op.degrid(x))
-        lam = float(torch.sum(z.double() * x.double()))
-        x = z / torch.linalg.vector_norm(z)
-    return lam

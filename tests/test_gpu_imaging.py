@@ -1,0 +1,87 @@
+"""Imaging loop on the GPU operator: power method and FISTA.
+
+On a 32^2 problem the GPU (all-FP64 path) and the oracle drive the same
+loop; the operators agree to the kernels' quadrature tolerance, so ||Phi||^2
+and the FISTA iterates agree to ~1e-6.  On the 2048^2, 5e6-visibility,
+8-stack workload a few FISTA iterations must lower the objective (by 27% in
+8 iterations when measured).
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operator, wkernel
+from paper_1903_06555_amd import imaging, wsp
+from paper_1903_06555_amd import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+
+class OracleOp:
+    def __init__(self, n, fov_deg, uvw, labels, centres):
+        self.ref = operator.StackedOperator(wkernel.Geometry(n=n, fov=math.radians(fov_deg)), uvw,
+                                            labels=labels, centres=centres)
+        self.n = n
+        self.device = torch.device("cpu")
+        self.real_dtype = torch.float64
+
+    def degrid(self, x):
+        return torch.from_numpy(self.ref.forward(x.cpu().numpy()))
+
+    def grid(self, y):
+        return torch.from_numpy(self.ref.adjoint(y.cpu().numpy()))
+
+
+def test_power_and_fista_match_oracle():
+    n, fov = 32, 10.0
+    uvw = syn.uniform_box_uvw(600, u_max=25.0, w_max=15.0, seed=23)
+    labels = np.zeros(len(uvw), dtype=np.int32)
+    centres = np.array([0.0])
+    ora = OracleOp(n, fov, uvw, labels, centres)
+    params = wsp.make_params(n, math.radians(fov), precision="fp64")
+    gpu = wsp.Operator(params, uvw, labels=labels, centres=centres)
+    try:
+        sky = syn.point_source_sky(n, 6, "exp", seed=24, margin=4)
+        y_cpu = ora.degrid(torch.from_numpy(sky))
+        L_o = imaging.power_norm2(ora, n_iter=60)
+        L_g = imaging.power_norm2(gpu, n_iter=60)
+        assert abs(L_g - L_o) <= 1e-6 * L_o, (L_g, L_o)
+        lam = 0.02 * float(torch.max(torch.abs(ora.grid(y_cpu))))
+        r_o = imaging.fista_l1(ora, y_cpu, lam, n_iter=60, norm2=L_o, track=False)
+        r_g = imaging.fista_l1(gpu, y_cpu.cuda(), lam, n_iter=60, norm2=L_o, track=False)
+        x_o, x_g = r_o.x.numpy(), r_g.x.cpu().numpy()
+        err = float(np.linalg.norm(x_g - x_o) / np.linalg.norm(x_o))
+        print(f"||Phi||^2 gpu {L_g:.9e} oracle {L_o:.9e}; FISTA iterate rel diff {err:.2e}", flush=True)
+        assert err <= 1e-5
+    finally:
+        gpu.close()
+
+
+def test_fista_lowers_objective_8_stacks():
+    wl = syn.WORKLOADS["mwa_2048_8_stacks"]
+    uvw = syn.workload_uvw(wl)
+    params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
+                             precision=wl.precision)
+    op = wsp.Operator(params, uvw)
+    try:
+        sky = torch.from_numpy(syn.workload_sky(wl)).cuda().float()
+        y = op.degrid(sky)
+        L = imaging.power_norm2(op, n_iter=20)
+        lam = 1e-3 * float(torch.max(torch.abs(op.grid(y))))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = imaging.fista_l1(op, y, lam, n_iter=8, norm2=L)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 8
+        print(f"FISTA: {dt * 1e3:.1f} ms per iteration (with objective), objective {res.objective[0]:.4e} -> "
+              f"{res.objective[-1]:.4e}", flush=True)
+        # deconvolving a 2048^2 dirty image converges slowly; after 8 iterations
+        # the objective has dropped by a good fraction and is at its lowest
+        assert res.objective[-1] < 0.8 * res.objective[0]
+        assert res.objective[-1] == min(res.objective)
+        assert float(res.x.min()) >= 0.0
+    finally:
+        op.close()

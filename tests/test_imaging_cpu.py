@@ -1,0 +1,83 @@
+"""Imaging loop (power method, FISTA) driven by the oracle operator on the CPU.
+
+The solver is pinned by facts that do not depend on its code: the power
+method must return the largest eigenvalue of the dense matrix of
+Re Phi^dagger Phi (built column by column, solved by numpy), and FISTA's
+result must satisfy the optimality (KKT) conditions of
+min 1/2 ||Phi x - y||^2 + lam ||x||_1, x >= 0:  with g = Re Phi^dagger (Phi x - y),
+g_i + lam = 0 where x_i > 0 and g_i + lam >= 0 where x_i = 0.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operator, wkernel
+from paper_1903_06555_amd import imaging
+from paper_1903_06555_amd import synthetic as syn
+
+
+class OracleOp:
+    """The oracle's Phi behind the operator interface the imaging module uses."""
+
+    def __init__(self, n, fov_deg, uvw):
+        self.ref = operator.StackedOperator(wkernel.Geometry(n=n, fov=math.radians(fov_deg)), uvw)
+        self.n = n
+        self.device = torch.device("cpu")
+        self.real_dtype = torch.float64
+
+    def degrid(self, x):
+        return torch.from_numpy(self.ref.forward(x.numpy()))
+
+    def grid(self, y):
+        return torch.from_numpy(self.ref.adjoint(y.numpy()))
+
+
+@pytest.fixture(scope="module")
+def small():
+    n = 16
+    uvw = syn.uniform_box_uvw(400, u_max=12.0, w_max=10.0, seed=21)
+    op = OracleOp(n, 10.0, uvw)
+    sky = np.zeros((n, n))
+    sky[5, 7], sky[10, 3], sky[8, 12] = 1.0, 0.6, 0.3
+    y = op.degrid(torch.from_numpy(sky))
+    return op, sky, y
+
+
+def test_power_method_matches_dense_eigenvalue(small):
+    op, sky, y = small
+    n = op.n
+    cols = []
+    for k in range(n * n):
+        e = np.zeros(n * n)
+        e[k] = 1.0
+        cols.append(op.grid(op.degrid(torch.from_numpy(e.reshape(n, n)))).numpy().ravel())
+    A = np.array(cols).T
+    assert np.allclose(A, A.T, atol=1e-9 * np.abs(A).max())  # Re Phi^dagger Phi is symmetric
+    top = float(np.linalg.eigvalsh(0.5 * (A + A.T))[-1])
+    est = imaging.power_norm2(op, n_iter=300, tol=1e-13)
+    # a Rayleigh quotient: never above the top eigenvalue, and close to it
+    assert est <= top * (1 + 1e-12), (est, top)
+    assert est >= top * (1 - 1e-3), (est, top)
+    assert imaging.power_norm2(op, n_iter=20, tol=0.0) <= est * (1 + 1e-12)
+
+
+def test_fista_reaches_kkt_point(small):
+    op, sky, y = small
+    L = imaging.power_norm2(op, n_iter=300, tol=1e-13)
+    lam = 0.01 * float(torch.max(torch.abs(op.grid(y))))
+    res = imaging.fista_l1(op, y, lam, n_iter=600, norm2=L)
+    x = res.x.numpy()
+    g = op.grid(op.degrid(res.x) - y).numpy()
+    scale = float(np.max(np.abs(op.grid(y).numpy())))
+    pos = x > 1e-9 * x.max()
+    assert pos.any()
+    assert np.max(np.abs(g[pos] + lam)) <= 1e-6 * scale
+    assert np.min(g[~pos] + lam) >= -1e-6 * scale
+    assert x.min() >= 0.0
+    # the objective settles
+    assert abs(res.objective[-1] - res.objective[-50]) <= 1e-9 * abs(res.objective[-1])
+    # the three sources are found at their pixels
+    for (j, i) in [(5, 7), (10, 3), (8, 12)]:
+        assert x[j, i] > 0.5 * sky[j, i]
