@@ -56,8 +56,9 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_file(workload: str) -> str:
-    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+def traffic_file(workload: str, precision: str) -> str:
+    suffix = "" if precision == "fp32_fp64phase" else f"_{precision}"
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}{suffix}.json")
 TRAFFIC_SOURCES = ("paper_1903_06555_amd/csrc/apply.hip", "paper_1903_06555_amd/csrc/wsp_internal.h",
                    "paper_1903_06555_amd/csrc/plan.hip")
 
@@ -71,17 +72,17 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, m: int):
+def measured_traffic(kernel: str, workload: str, m: int, precision: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     readings (calibrated on a plain copy), or None if they were taken on other
-    kernel sources or another workload."""
+    kernel sources, another workload or another precision."""
     try:
-        with open(traffic_file(workload)) as fh:
+        with open(traffic_file(workload, precision)) as fh:
             rec = json.load(fh)
     except OSError:
         return None
     if rec.get("source_sha256") != source_digest() or rec.get("workload") != workload \
-            or rec.get("m_vis") != m:
+            or rec.get("m_vis") != m or rec.get("precision", "fp32_fp64phase") != precision:
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
@@ -432,7 +433,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, wl.name, m),
+                     "traffic": measured_traffic(dom, wl.name, m, precision),
                      "algorithmic_bytes": traffic, "avg_launch_ms": per_launch[dom]},
         "stages_ms_per_launch": per_launch,
         "setup": {"plan_s": t_plan, "build_s": t_build, "build_mvis_per_s": m / t_build / 1e6,

@@ -32,3 +32,13 @@ def test_generators_are_seeded():
     assert np.array_equal(syn.random_vis(10, 3), syn.random_vis(10, 3))
     x = syn.point_source_sky(64, 20, "gaussian", 1)
     assert np.count_nonzero(x) <= 20 and x.shape == (64, 64)
+
+
+def test_traffic_record_matches_sources_workload_and_precision():
+    import bench
+    rec = bench.measured_traffic("grid", "mwa_1024_single_stack", 1_000_000, "fp32_fp64phase")
+    assert rec is None or rec > 0
+    # another precision, visibility count or workload never borrows that record
+    assert bench.measured_traffic("grid", "mwa_1024_single_stack", 1_000_000, "fp64") is None
+    assert bench.measured_traffic("grid", "mwa_1024_single_stack", 999_999, "fp32_fp64phase") is None
+    assert bench.measured_traffic("grid", "no_such_workload", 1_000_000, "fp32_fp64phase") is None
