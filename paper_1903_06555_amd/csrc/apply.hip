@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     constexpr int kPer = 64 / kGroup;  // entries per wavefront pass
-    constexpr int kU = 4;              // loads per lane in flight
+    constexpr int kU = 8;              // load slots per lane
     __shared__ C tile[kTile * kTile];
     __shared__ int s_geo[kChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int s_idx[kChunk];
@@ -471,13 +471,20 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
             for (int k0 = 0; __any(k0 < ntap); k0 += kGroup * kU) {
                 C K[kU];
                 int li[kU];
+                // slots past every group's entry are skipped (uniform), lanes past
+                // their own entry load nothing and add zero
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    // past the entry: re-read its tap 0 and weight it by zero below
-                    const int k = k0 + kGroup * u + gl < ntap ? k0 + kGroup * u + gl : 0;
-                    const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in k_degrid_tiles
-                    li[u] = cell0 + row * kTile + (k - row * nc);
-                    K[u] = load_tap(&tp[k]);
+                    K[u].x = 0;
+                    K[u].y = 0;
+                    li[u] = cell0;
+                    const bool ok = k0 + kGroup * u + gl < ntap;
+                    if (__any(ok)) {
+                        const int k = ok ? k0 + kGroup * u + gl : 0;
+                        const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in k_degrid_tiles
+                        li[u] = cell0 + row * kTile + (k - row * nc);
+                        if (ok) K[u] = load_tap(&tp[k]);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
