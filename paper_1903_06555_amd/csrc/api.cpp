@@ -57,6 +57,62 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+void destroy_row_plans(wsp_ctx *c) {
+    if (c->fft_ulo_made) hipfftDestroy(c->fft_ulo);
+    if (c->fft_ujoin_made) hipfftDestroy(c->fft_ujoin);
+    if (c->fft_uhi_made) hipfftDestroy(c->fft_uhi);
+    c->fft_ulo_made = c->fft_ujoin_made = c->fft_uhi_made = false;
+    c->fft_work = c->fft_work_base;
+    c->g.rows_lo = c->g.G;
+    c->g.rows_hi = 0;
+}
+
+// The grid rows that hold work items (tile rows of the item keys), and
+// batched plans for the U passes over just those rows when they leave at
+// least a quarter of the grid out.
+hipfftResult make_row_plans(wsp_ctx *c) {
+    destroy_row_plans(c);
+    const Plan &pl = c->plan;
+    const int G = c->g.G, T = G / kTile, K = c->g.n_stacks;
+    if (pl.n_items == 0) return HIPFFT_SUCCESS;
+    std::vector<uint32_t> keys((size_t)pl.n_items);
+    if (hipMemcpy(keys.data(), pl.item_key, sizeof(uint32_t) * keys.size(), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return HIPFFT_EXEC_FAILED;
+    const uint32_t tmask = (1u << pl.tile_bits) - 1;
+    int lo_t = 0, hi_t = 0;
+    for (uint32_t key : keys) {
+        const int ty = (int)((key >> pl.tile_bits) & tmask);
+        if (ty < T / 2) lo_t = ty + 1 > lo_t ? ty + 1 : lo_t;
+        else hi_t = T - ty > hi_t ? T - ty : hi_t;
+    }
+    const int rows_lo = lo_t * kTile, rows_hi = hi_t * kTile;
+    if (4 * (rows_lo + rows_hi) > 3 * G) return HIPFFT_SUCCESS;  // not worth it
+    const hipfftType ty = c->p.precision == WSP_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C;
+    int len[1] = {G};
+    auto make = [&](hipfftHandle *h, bool *made, int batch) -> hipfftResult {
+        if (batch <= 0) return HIPFFT_SUCCESS;
+        hipfftResult r = hipfftCreate(h);
+        if (r != HIPFFT_SUCCESS) return r;
+        *made = true;
+        hipfftSetAutoAllocation(*h, 0);
+        size_t w = 0;
+        r = hipfftMakePlanMany(*h, 1, len, nullptr, 1, G, nullptr, 1, G, ty, batch, &w);
+        if (w > c->fft_work) c->fft_work = w;
+        return r;
+    };
+    hipfftResult r = make(&c->fft_ulo, &c->fft_ulo_made, rows_lo);
+    if (r == HIPFFT_SUCCESS && K > 1) r = make(&c->fft_ujoin, &c->fft_ujoin_made, rows_lo + rows_hi);
+    if (r == HIPFFT_SUCCESS) r = make(&c->fft_uhi, &c->fft_uhi_made, rows_hi);
+    if (r != HIPFFT_SUCCESS) {
+        destroy_row_plans(c);
+        return r;
+    }
+    c->g.rows_lo = rows_lo;
+    c->g.rows_hi = rows_hi;
+    return HIPFFT_SUCCESS;
+}
+
 wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
     int support_err = 0;
     hipError_t e = make_plan(c, c->plan_centres, s, &support_err);
@@ -68,6 +124,11 @@ wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
     if (support_err & 2) {
         c->planned = false;
         return fail(WSP_EINVAL, "a visibility lies beyond 1e9 grid cells");
+    }
+    hipfftResult fr = make_row_plans(c);
+    if (fr != HIPFFT_SUCCESS) {
+        c->planned = false;
+        return fail(WSP_EHIP, "hipfftMakePlanMany (row bands) failed (" + std::to_string((int)fr) + ")");
     }
     c->planned = true;
     c->bound = false;
@@ -209,6 +270,8 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     double rho_c = p.fov_rad * std::sqrt(0.5);
     double n_c = std::sqrt(1.0 - rho_c * rho_c);
     g.slope = (rho_c / (n_c * g.du)) * p.support_scale;
+    g.rows_lo = g.G;  // all grid rows, until a plan narrows them
+    g.rows_hi = 0;
     double xr = 2.0 * M_PI * g.a * g.r_max;
     double ymax = std::fmax(0.25 * g.beta * g.beta, std::fabs(0.25 * (g.beta * g.beta - xr * xr)));
     int terms = (int)std::ceil(2.0 * std::sqrt(ymax)) + 30;
@@ -250,7 +313,10 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
             delete c;
             return fail(WSP_EHIP, "hipfftMakePlanMany failed (" + std::to_string((int)r) + ")");
         }
-        c->fft_work = wv > wu ? wv : wu;  // the two passes run in turn: one work area
+        c->fft_work = wv > wu ? wv : wu;  // the passes run in turn: one work area
+        c->fft_work_base = c->fft_work;
+        c->g.rows_lo = g.G;
+        c->g.rows_hi = 0;
     }
     e = hipMalloc(&c->plan_centres, sizeof(double) * g.n_stacks);
     if (e != hipSuccess) {
@@ -399,9 +465,14 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
         return fail(WSP_ENOMEM_BINDING, "buffer smaller than wsp_footprint");
     if (((uintptr_t)kernels | (uintptr_t)grids | (uintptr_t)scratch) & 255u)
         return fail(WSP_EINVAL, "buffers must be 256-byte aligned");
-    if (c->fft_work > 0 && (hipfftSetWorkArea(c->fft_v, scratch) != HIPFFT_SUCCESS ||
-                            hipfftSetWorkArea(c->fft_u, scratch) != HIPFFT_SUCCESS))
-        return fail(WSP_EHIP, "hipfftSetWorkArea failed");
+    if (c->fft_work > 0) {
+        bool ok = hipfftSetWorkArea(c->fft_v, scratch) == HIPFFT_SUCCESS &&
+                  hipfftSetWorkArea(c->fft_u, scratch) == HIPFFT_SUCCESS;
+        if (c->fft_ulo_made) ok = ok && hipfftSetWorkArea(c->fft_ulo, scratch) == HIPFFT_SUCCESS;
+        if (c->fft_ujoin_made) ok = ok && hipfftSetWorkArea(c->fft_ujoin, scratch) == HIPFFT_SUCCESS;
+        if (c->fft_uhi_made) ok = ok && hipfftSetWorkArea(c->fft_uhi, scratch) == HIPFFT_SUCCESS;
+        if (!ok) return fail(WSP_EHIP, "hipfftSetWorkArea failed");
+    }
     c->scratch_half = (char *)scratch + align256(c->fft_work);
     c->scratch_yw = (char *)c->scratch_half + align256(half_bytes(c));
     c->scratch_dpart = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
@@ -553,6 +624,7 @@ void wsp_destroy(wsp_ctx *c) {
     hipFree(c->plan_centres);
     if (c->fft_v_made) hipfftDestroy(c->fft_v);
     if (c->fft_u_made) hipfftDestroy(c->fft_u);
+    destroy_row_plans(c);
     delete c;
 }
 

@@ -133,6 +133,7 @@ template <typename C>
 __global__ __launch_bounds__(256) void k_transpose_pad(const C *__restrict__ half, C *grids, Geom g) {
     __shared__ C s_t[kT][kT + 1];  // [U offset][V offset]
     const int V0 = blockIdx.x * kT, U0 = blockIdx.y * kT, k = blockIdx.z;
+    if (!row_used(V0, g)) return;  // rows that no work item reads (uniform)
     for (int e = threadIdx.x; e < kT * kT; e += 256) {
         const int u = e / kT, v = e % kT;  // along V: coalesced reads of H
         const int i = pixel_of(U0 + u, g);
@@ -156,13 +157,14 @@ __global__ __launch_bounds__(256) void k_transpose_crop(const C *__restrict__ gr
     __shared__ C s_t[kT][kT + 1];  // [V offset][i offset]
     const int V0 = blockIdx.x * kT, i0 = blockIdx.y * kT, k = blockIdx.z;
     const C *src = grids + (int64_t)k * g.G * g.G;
+    const bool used = row_used(V0, g);  // rows without work items hold zeros (uniform)
     for (int e = threadIdx.x; e < kT * kT; e += 256) {
         const int v = e / kT, cc = e % kT;  // along i (U): coalesced grid reads
         const int i = i0 + cc;
         C z;
         z.x = 0;
         z.y = 0;
-        if (i < g.n) z = src[(int64_t)(V0 + v) * g.G + padded_of(i, g)];
+        if (used && i < g.n) z = src[(int64_t)(V0 + v) * g.G + padded_of(i, g)];
         s_t[v][cc] = z;
     }
     __syncthreads();
@@ -209,15 +211,21 @@ __global__ __launch_bounds__(256) void k_crop_half(const typename Types<kFP64>::
     }
 }
 
+// Zero the used rows of the grids (the others are never read).
 template <typename C>
-__global__ void k_zero(C *x, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        C z;
-        z.x = 0;
-        z.y = 0;
-        x[i] = z;
-    }
+__global__ void k_zero_rows(C *grids, Geom g) {
+    const int rows = g.rows_lo + g.rows_hi;
+    const int64_t n = (int64_t)g.n_stacks * rows * g.G;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t kr = i / g.G;
+    const int U = (int)(i - kr * g.G);
+    const int k = (int)(kr / rows), r = (int)(kr - (int64_t)k * rows);
+    const int V = r < g.rows_lo ? r : g.G - g.rows_hi + (r - g.rows_lo);
+    C z;
+    z.x = 0;
+    z.y = 0;
+    grids[((int64_t)k * g.G + V) * g.G + U] = z;
 }
 
 struct ApplyArgs {
@@ -829,6 +837,26 @@ hipfftResult fft_pass(hipfftHandle plan, C *data, int dir, hipStream_t s) {
     }
 }
 
+// The U pass over the used rows of every stack: rows [0, rows_lo) of stack
+// 0, then each stack's top band with the next stack's bottom band (adjacent
+// in memory), then the last stack's top band.
+template <typename C>
+hipError_t u_pass(wsp_ctx *c, C *grids, int dir, hipStream_t s) {
+    const Geom &g = c->g;
+    if (g.rows_lo >= g.G) return fft_pass(c->fft_u, grids, dir, s) == HIPFFT_SUCCESS ? hipSuccess : hipErrorUnknown;
+    const int64_t GG = (int64_t)g.G * g.G;
+    if (c->fft_ulo_made && fft_pass(c->fft_ulo, grids, dir, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+    for (int k = 0; k + 1 < g.n_stacks; ++k) {
+        C *band = grids + k * GG + (int64_t)(g.G - g.rows_hi) * g.G;
+        if (fft_pass(c->fft_ujoin, band, dir, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+    }
+    if (c->fft_uhi_made) {
+        C *band = grids + (int64_t)(g.n_stacks - 1) * GG + (int64_t)(g.G - g.rows_hi) * g.G;
+        if (fft_pass(c->fft_uhi, band, dir, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+    }
+    return hipSuccess;
+}
+
 // F (forward, from H to the grids) or F^dagger (backward, from the grids to H),
 // both unnormalised.
 template <typename C>
@@ -842,11 +870,13 @@ hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
                            (const C *)half, grids, g);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (fft_pass(c->fft_u, grids, HIPFFT_FORWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+        e = u_pass<C>(c, grids, HIPFFT_FORWARD, s);
+        if (e != hipSuccess) return e;
     } else {
-        if (fft_pass(c->fft_u, grids, HIPFFT_BACKWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
+        hipError_t e = u_pass<C>(c, grids, HIPFFT_BACKWARD, s);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_transpose_crop<C>, tgrid, dim3(256), 0, s, (const C *)grids, half, g);
-        hipError_t e = hipGetLastError();
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (fft_pass(c->fft_v, half, HIPFFT_BACKWARD, s) != HIPFFT_SUCCESS) return hipErrorUnknown;
     }
@@ -897,9 +927,9 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     const Geom &g = c->g;
-    int64_t ncell = (int64_t)g.G * g.G * g.n_stacks;
+    const int64_t ncell = (int64_t)(g.rows_lo + g.rows_hi) * g.G * g.n_stacks;
     hipEvent_t ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_zero<C>, dim3(blocks(ncell, 256)), dim3(256), 0, s, (C *)c->grids, ncell);
+    hipLaunchKernelGGL(k_zero_rows<C>, dim3(blocks(ncell, 256)), dim3(256), 0, s, (C *)c->grids, g);
     stage_end(c, kStZero, ev, s);
     ApplyArgs a = make_args(c);
     const Plan &pl = c->plan;

@@ -35,7 +35,15 @@ struct Geom {
     double a;            // J / 2
     double taper_norm;   // 2 pi a^2 / I0(beta)
     double slope;        // support slope s f (cells per wavelength of |w - wbar|)
+    // grid rows that hold work items: [0, rows_lo) and [G - rows_hi, G) of
+    // every stack (rows_lo = G, rows_hi = 0 when the pruning does not pay)
+    int rows_lo;
+    int rows_hi;
 };
+
+__host__ __device__ inline bool row_used(int V, const Geom &g) {
+    return V < g.rows_lo || V >= g.G - g.rows_hi;
+}
 
 // Tap layout.  A visibility's J_p x J_p taps occupy one contiguous block
 // (at tap_off[p]).  Inside it the taps are grouped by the 64 x 64 grid tile
@@ -128,6 +136,12 @@ struct wsp_ctx {
     // pixels), and along U over the K x G rows of the grids
     hipfftHandle fft_v = 0, fft_u = 0;
     bool fft_v_made = false, fft_u_made = false;
+    // U passes over the used rows only (see Geom::rows_lo): batches of
+    // rows_lo, rows_hi + rows_lo (one stack's top band and the next stack's
+    // bottom band are adjacent) and rows_hi rows
+    hipfftHandle fft_ulo = 0, fft_ujoin = 0, fft_uhi = 0;
+    bool fft_ulo_made = false, fft_ujoin_made = false, fft_uhi_made = false;
+    size_t fft_work_base = 0;  // work area of fft_v and fft_u
     size_t fft_work = 0;
     wsp::Plan plan;
     bool planned = false;
