@@ -281,6 +281,17 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     return (b % nx) * per + b / nx;
 }
 
+// The same for kH blocks per item: the blocks of an item go to one XCD (8
+// block indices apart), so rows of an entry split between them share that
+// XCD's L2.  *part = which block of the item.
+__device__ __forceinline__ int xcd_item_part(int b, int n, int kH, int *part) {
+    const int nx = 8;
+    const int r = b / nx;
+    *part = r % kH;
+    const int per = (n + nx - 1) / nx;
+    return (b % nx) * per + r / kH;
+}
+
 // First cell of a (stack, tile) key in the grids.
 template <typename C>
 __device__ __forceinline__ C *tile_origin(C *grids, uint32_t key, const TileArgs &t) {
@@ -562,8 +573,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
     __shared__ int64_t s_off[kGChunk];
     __shared__ C s_y[kGChunk];
     static_assert(kGChunk <= kThreads / kH, "one thread stages one entry");
-    const int part = blockIdx.x % kH;
-    const int item = xcd_item(blockIdx.x / kH, t.n_items);
+    int part;
+    const int item = xcd_item_part(blockIdx.x, t.n_items, kH, &part);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
     const int lrow0 = (threadIdx.x >> 6) * kBand;  // band start in the LDS tile
@@ -675,8 +686,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
     __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int64_t s_off[kGChunk];
     __shared__ C s_y[kGChunk];
-    const int part = blockIdx.x % kH;
-    const int item = xcd_item(blockIdx.x / kH, t.n_items);
+    int part;
+    const int item = xcd_item_part(blockIdx.x, t.n_items, kH, &part);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
     const int lrow0 = (threadIdx.x >> 6) * kBand;  // band start in the LDS tile
