@@ -327,6 +327,21 @@ __device__ __forceinline__ double2 load_tap(const double2 *p) {
     return make_double2(t.x, t.y);
 }
 
+// Row and column of tap k in a row-major sub-block nc wide.  (k + 1/2) / nc
+// is never within 1/(2 nc) of an integer, and (k + 1/2) * rcp(nc) with the
+// hardware reciprocal (1 ulp) is off by < 4096 * 2.4e-7 < 1/128 <= 1/(2 nc),
+// so the row is exact; both products fit the 24-bit multiplier.
+__device__ __forceinline__ float recip_nc(int nc) { return __builtin_amdgcn_rcpf((float)nc); }
+__device__ __forceinline__ int sub_row(int k, float inv_nc) { return (int)(((float)k + 0.5f) * inv_nc); }
+__device__ __forceinline__ int sub_cell(int cell0, int k, int row, int nc) {
+    return cell0 + row * kTile + (k - (int)__umul24((unsigned)row, (unsigned)nc));
+}
+
+// The wavefront's index in its block, known to the compiler as uniform over
+// the wavefront (so that everything derived from it stays in scalar registers
+// and scalar branches).
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // value of lane l (l uniform over the wavefront)
 __device__ __forceinline__ float bcast(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -383,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
             tile[i] = src[(int64_t)(i / kTile) * t.G + (i % kTile)];
     }
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
+    const int wid = wave_index();
     const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
     for (int base = s_beg; base < s_end; base += kChunk) {
         const int n = (s_end - base < kChunk) ? s_end - base : kChunk;
@@ -400,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
             const int nc = geo & 255, nr = (geo >> 8) & 255;
             const int lx0 = (geo >> 16) & 255, ly0 = (geo >> 24) & 255;
             const C *tp = taps + s_off[j];
-            const float inv_nc = 1.0f / (float)nc;
+            const float inv_nc = recip_nc(nc);
             const int ntap = nr * nc;
             const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
             R ar = 0, ai = 0;
@@ -412,9 +427,8 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
                 for (int u = 0; u < U; ++u) {
                     // past the sub-block: re-read tap 0 and weight it by zero below
                     const int k = k0 + 64 * u + lane < ntap ? k0 + 64 * u + lane : 0;
-                    // (k + 1/2) / nc is never within 1/(2 nc) of an integer: exact row
-                    const int row = (int)(((float)k + 0.5f) * inv_nc);
-                    li[u] = cell0 + row * kTile + (k - row * nc);
+                    const int row = sub_row(k, inv_nc);
+                    li[u] = sub_cell(cell0, k, row, nc);
                     K[u] = load_tap(&tp[k]);  // the sub-block is contiguous, row-major
                 }
 #pragma unroll
@@ -463,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
             tile[i] = src[(int64_t)(i / kTile) * t.G + (i % kTile)];
     }
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
+    const int wid = wave_index();
     const int grp = lane / kGroup, gl = lane % kGroup;
     const int s_beg = t.item_start[item], s_end = t.item_start[item + 1];
     for (int base = s_beg; base < s_end; base += kChunk) {
@@ -483,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
             const int nc = geo & 255, nr = (geo >> 8) & 255;
             const int lx0 = (geo >> 16) & 255, ly0 = (geo >> 24) & 255;
             const C *tp = taps + s_off[valid ? j : j0];
-            const float inv_nc = 1.0f / (float)nc;
+            const float inv_nc = recip_nc(nc);
             const int ntap = valid ? nr * nc : 0;
             const int cell0 = ly0 * kTile + lx0;
             R ar = 0, ai = 0;
@@ -500,8 +514,8 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
                     const bool ok = k0 + kGroup * u + gl < ntap;
                     if (__any(ok)) {
                         const int k = ok ? k0 + kGroup * u + gl : 0;
-                        const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in k_degrid_tiles
-                        li[u] = cell0 + row * kTile + (k - row * nc);
+                        const int row = sub_row(k, inv_nc);
+                        li[u] = sub_cell(cell0, k, row, nc);
                         if (ok) K[u] = load_tap(&tp[k]);
                     }
                 }
@@ -568,7 +582,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                                                          typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
     constexpr int kRows = kTile / kH;  // tile rows of this block
-    __shared__ C tile[kRows * kTile];
+    __shared__ C tile[kRows * kTile + 1];  // + a spare cell for lanes without a tap
     __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int64_t s_off[kGChunk];
     __shared__ C s_y[kGChunk];
@@ -577,7 +591,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
     const int item = xcd_item_part(blockIdx.x, t.n_items, kH, &part);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
-    const int lrow0 = (threadIdx.x >> 6) * kBand;  // band start in the LDS tile
+    const int lrow0 = wave_index() * kBand;  // band start in the LDS tile
     const int band0 = part * kRows + lrow0;       // and in the grid tile
     C zero;
     zero.x = 0;
@@ -624,31 +638,34 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                 const int nc = ez & 255, lx0 = (ez >> 16) & 255;
                 const C *tp = taps + off;
                 const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
-                const float inv_nc = 1.0f / (float)nc;
+                const float inv_nc = recip_nc(nc);
                 const int cell0 = (ly0 - part * kRows) * kTile + lx0;  // LDS cell of sub-block tap 0
                 for_batches(kbeg, kend, [&](int k0, auto ucount) {
                     constexpr int U = decltype(ucount)::value;
                     C K[U], z[U];
                     int li[U];
-                    // past the run: re-read its first tap; that lane stores nothing
+                    // past the run: re-read its first tap and add zero to the spare cell
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int k = k0 + 64 * u + lane < kend ? k0 + 64 * u + lane : kbeg;
-                        const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in degrid
-                        li[u] = cell0 + row * kTile + (k - row * nc);
+                        const bool ok = k0 + 64 * u + lane < kend;
+                        const int k = ok ? k0 + 64 * u + lane : kbeg;
+                        const int row = sub_row(k, inv_nc);
+                        li[u] = ok ? sub_cell(cell0, k, row, nc) : kRows * kTile;
                         K[u] = load_tap(&tp[k]);
                     }
-                    // all reads before all writes: the U x 64 cells are distinct
+                    // all reads before all writes: the cells of the U x 64 taps are
+                    // distinct (only the spare cell repeats)
 #pragma unroll
                     for (int u = 0; u < U; ++u) z[u] = tile[li[u]];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        if (k0 + 64 * u + lane < kend) {
-                            C o;
-                            o.x = z[u].x + (K[u].x * y.x + K[u].y * y.y);
-                            o.y = z[u].y + (K[u].x * y.y - K[u].y * y.x);
-                            tile[li[u]] = o;
-                        }
+                        const bool ok = k0 + 64 * u + lane < kend;
+                        using R = decltype(K[u].x);
+                        const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
+                        C o;
+                        o.x = z[u].x + (kr * y.x + ki * y.y);
+                        o.y = z[u].y + (kr * y.y - ki * y.x);
+                        tile[li[u]] = o;
                     }
                 });
             }
@@ -682,7 +699,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                                                                         typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
     constexpr int kRows = kTile / kH;  // tile rows of this block
-    __shared__ C tile[kRows * kTile];
+    __shared__ C tile[kRows * kTile + 1];  // + a spare cell for lanes without a tap
     __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int64_t s_off[kGChunk];
     __shared__ C s_y[kGChunk];
@@ -690,7 +707,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
     const int item = xcd_item_part(blockIdx.x, t.n_items, kH, &part);
     if (item >= t.n_items) return;  // uniform over the block
     const int lane = threadIdx.x & 63;
-    const int lrow0 = (threadIdx.x >> 6) * kBand;  // band start in the LDS tile
+    const int lrow0 = wave_index() * kBand;  // band start in the LDS tile
     const int band0 = part * kRows + lrow0;       // and in the grid tile
     C zero;
     zero.x = 0;
@@ -729,7 +746,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                 int li[kSlots], ys[kSlots];
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
-                    li[sl] = -1;
+                    li[sl] = kRows * kTile;  // lanes without a tap update the spare cell by zero
                     if (k0 >= kend && hits) {  // next entry with rows in the band
                         const int l = __builtin_ctzll(hits);
                         hits &= hits - 1;
@@ -745,7 +762,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                         kbeg = (lo - ly0) * nc;
                         kend = (hi - ly0) * nc;
                         k0 = kbeg;
-                        inv_nc = 1.0f / (float)nc;
+                        inv_nc = recip_nc(nc);
                         cell0 = (ly0 - part * kRows) * kTile + ((ez >> 16) & 255);
                     }
                     K[sl] = zero;
@@ -753,8 +770,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                     if (k0 < kend) {  // uniform: this slot takes taps [k0, k0 + 64) of the run
                         const bool ok = k0 + lane < kend;
                         const int k = ok ? k0 + lane : kbeg;
-                        const int row = (int)(((float)k + 0.5f) * inv_nc);  // exact, as in degrid
-                        li[sl] = ok ? cell0 + row * kTile + (k - row * nc) : -1;
+                        const int row = sub_row(k, inv_nc);
+                        li[sl] = ok ? sub_cell(cell0, k, row, nc) : kRows * kTile;  // else: the spare cell
                         K[sl] = load_tap(&tp[k]);
                         k0 += 64;
                     }
@@ -762,13 +779,11 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
                     const auto yx = bcast(y_l.x, ys[sl]), yy = bcast(y_l.y, ys[sl]);
-                    if (li[sl] >= 0) {
-                        const C z = tile[li[sl]];
-                        C o;
-                        o.x = z.x + (K[sl].x * yx + K[sl].y * yy);
-                        o.y = z.y + (K[sl].x * yy - K[sl].y * yx);
-                        tile[li[sl]] = o;
-                    }
+                    const C z = tile[li[sl]];
+                    C o;
+                    o.x = z.x + (K[sl].x * yx + K[sl].y * yy);
+                    o.y = z.y + (K[sl].x * yy - K[sl].y * yx);
+                    tile[li[sl]] = o;
                 }
             }
         }
