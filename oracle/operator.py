@@ -55,12 +55,15 @@ def crop(geom: Geometry, big):
 
 
 class StackedOperator:
-    """Phi for one set of visibilities, with per-visibility exact kernels."""
+    """Phi for one set of visibilities, with a kernel per visibility (exact by default)."""
 
     def __init__(self, geom: Geometry, uvw, weights=None, n_stacks: int = 1,
                  fold: bool = False, labels=None, centres=None,
-                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100):
+                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, kernel_fn=None):
         self.geom = geom
+        # (u_pix, v_pix, w_eff, geom, jp) -> (U0, V0, K): exact Eq. (6) taps by
+        # default, or e.g. presample.PlaneSampler(...).visibility_kernel
+        self.kernel_fn = wkernel.visibility_kernel if kernel_fn is None else kernel_fn
         uvw = np.asarray(uvw, dtype=np.float64)
         self.m = uvw.shape[0]
         if fold:
@@ -87,7 +90,7 @@ class StackedOperator:
     def kernel(self, p: int):
         """(U0, V0, K[J_p, J_p]) of visibility p (cached)."""
         if p not in self._kernels:
-            self._kernels[p] = wkernel.visibility_kernel(
+            self._kernels[p] = self.kernel_fn(
                 self.u_pix[p], self.v_pix[p], self.w_eff[p], self.geom, int(self.jp[p]))
         return self._kernels[p]
 
