@@ -59,6 +59,9 @@ typedef int32_t wsp_status;
 #define WSP_FP32_FP64PHASE 0      /* FP32 data and taps, FP64 phase arguments */
 #define WSP_FP64 1                /* FP64 everywhere                          */
 
+#define WSP_KERNELS_EXACT 0       /* one set of J_p x J_p taps per visibility (Eq. (6))   */
+#define WSP_KERNELS_PLANES 1      /* taps interpolated on the fly from 1-D w-planes     */
+
 typedef struct wsp_params {
     int32_t n;              /* image side N, even, multiple of 32                       */
     double oversample;      /* alpha; alpha*N must be an integer multiple of 64         */
@@ -76,7 +79,32 @@ typedef struct wsp_params {
     double kmeans_tol;      /* Algorithm 1 convergence (the paper uses 1e-3, Sec. 4)    */
     int32_t kmeans_max_iter;/* iteration cap of Algorithm 1                             */
     int32_t device;         /* HIP device ordinal                                       */
+    int32_t kernel_mode;    /* WSP_KERNELS_EXACT or WSP_KERNELS_PLANES (see below)      */
+    double plane_dq;        /* w-plane mode: sample step in q (cells); 0 selects 1/64   */
+    double plane_dw;        /* w-plane mode: plane step in |w| (wavelengths); 0: 1/16   */
 } wsp_params;
+
+/* Kernel modes.
+ *
+ * WSP_KERNELS_EXACT: wsp_build_kernels integrates Eq. (6) for every tap of
+ * every visibility and stores the taps (sum_p J_p^2 complex values).
+ *
+ * WSP_KERNELS_PLANES (Sec. 5.1.1, bilinear interpolation between w-planes):
+ * radial symmetry makes the kernel a function of the tap distance q and w
+ * only, so wsp_build_kernels integrates Eq. (6) on the lattice
+ * T[j, i] = K(i dq, j dw), q, w >= 0 (the pre-sampled 1-D w-planes), and
+ * degrid and grid evaluate every tap on the fly by bilinear interpolation:
+ * with a = |w_eff| / dw, j = floor(a), s = a - j, x = q / dq, i = floor(x),
+ * t = x - i,
+ *     K~ = (1 - s)[(1 - t) T[j, i] + t T[j, i+1]] + s[(1 - t) T[j+1, i] + t T[j+1, i+1]],
+ * conjugated when w_eff < 0 (K(q, -w) = conj K(q, w)).  No per-visibility
+ * taps are stored: the "kernel" buffer holds the lattice instead, as complex64
+ * pairs (T[j, i], T[j+1, i]) for j = 0 .. floor(max|w_eff| / dw) and i up to
+ * the largest tap distance of a support at |w| = (j + 1) dw.  Supports, the
+ * tile work lists and every other part of the operator are those of the exact
+ * mode.  Only with precision WSP_FP32_FP64PHASE.  The interpolation error with
+ * the default steps is about 1e-4 of the kernel peak on 25-degree fields
+ * (bilinear error ~ dq^2/8 max|d2K/dq2| + dw^2/8 max|d2K/dw2|). */
 
 typedef struct wsp_ctx wsp_ctx;
 
@@ -120,7 +148,8 @@ wsp_status wsp_get_stacks(const wsp_ctx *ctx, int32_t *labels, double *centres,
 wsp_status wsp_get_support(const wsp_ctx *ctx, int32_t *jp, uint8_t *folded);
 
 /* Exact byte sizes of the caller-owned buffers after wsp_set_uvw:
- * kernel taps (sum_p J_p^2 complex values), the K Fourier grids (K G^2
+ * kernel taps (sum_p J_p^2 complex values; in w-plane mode the w-plane
+ * lattice instead, 16 bytes per sample pair), the K Fourier grids (K G^2
  * complex values) and scratch (FFT work area, M complex values, one complex
  * partial sum per (visibility, grid tile) overlap, and one 64 x 64 complex
  * partial tile per work item of a grid tile split over several items).
@@ -142,14 +171,17 @@ wsp_status wsp_bind_memory(wsp_ctx *ctx, void *kernels, size_t kernel_bytes,
  * g = 2-D Fourier transform of the radial KB blob, by adaptive Gauss-Kronrod
  * (7, 15) quadrature with the tolerances of the parameters.  Blocks until
  * complete.  Returns WSP_WARN_QUAD_MAXEVAL if a visibility reached
- * quad_max_panels.  Errors: WSP_ESTATE, WSP_ENOMEM_BINDING, WSP_EHIP. */
+ * quad_max_panels.  In w-plane mode it integrates the lattice of w-planes
+ * with the same quadrature and tolerances instead.
+ * Errors: WSP_ESTATE, WSP_ENOMEM_BINDING, WSP_EHIP. */
 wsp_status wsp_build_kernels(wsp_ctx *ctx, void *stream);
 
 /* The same build for the visibilities first .. first+count-1 of the build
  * order (costliest first), so a caller can report progress on long builds.
  * Parts must follow each other from first = 0; the operator is usable once
- * all M are built.  Errors: as wsp_build_kernels, WSP_EINVAL (range),
- * WSP_ESTATE (out of order). */
+ * all M are built.  In w-plane mode the part starting at 0 builds the whole
+ * lattice and later parts only advance the count.  Errors: as
+ * wsp_build_kernels, WSP_EINVAL (range), WSP_ESTATE (out of order). */
 wsp_status wsp_build_kernels_part(wsp_ctx *ctx, int64_t first, int64_t count, void *stream);
 
 /* Quadrature statistics of the last build: total panels, and visibilities
@@ -173,7 +205,8 @@ wsp_status wsp_grid(wsp_ctx *ctx, const void *vis, void *image, void *stream);
 /* Test hook: copy the taps of visibility p (caller order) to host memory
  * (complex, J_p^2 values, row-major [row][col], rows along v) and return J_p
  * and the unwrapped base indices U0, V0.  out may be NULL to query J_p only.
- * Synchronises the device.  Errors: WSP_ESTATE, WSP_EINVAL. */
+ * In w-plane mode the taps are interpolated from the lattice as degrid and
+ * grid do.  Synchronises the device.  Errors: WSP_ESTATE, WSP_EINVAL, WSP_EHIP. */
 wsp_status wsp_kernel_values(wsp_ctx *ctx, int64_t p, void *out, int32_t *jp,
                              int32_t *u0, int32_t *v0);
 

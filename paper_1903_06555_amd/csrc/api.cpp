@@ -125,6 +125,15 @@ wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
         c->planned = false;
         return fail(WSP_EINVAL, "a visibility lies beyond 1e9 grid cells");
     }
+    if (c->g.planes) {
+        bool too_large = false;
+        e = plane_setup(c, s, &too_large);
+        if (e != hipSuccess) return hip_fail(e, "w-plane layout");
+        if (too_large) {
+            c->planned = false;
+            return fail(WSP_EINVAL, "w-plane lattice above 2^31 sample pairs: raise plane_dq or plane_dw");
+        }
+    }
     hipfftResult fr = make_row_plans(c);
     if (fr != HIPFFT_SUCCESS) {
         c->planned = false;
@@ -252,6 +261,13 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     if (!(p.kmeans_tol >= 0.0) || p.kmeans_max_iter < 1)
         return fail(WSP_EINVAL, "kmeans_tol must be >= 0 and kmeans_max_iter >= 1");
     if (p.device < 0) return fail(WSP_EINVAL, "device must be >= 0");
+    if (p.kernel_mode != WSP_KERNELS_EXACT && p.kernel_mode != WSP_KERNELS_PLANES)
+        return fail(WSP_EINVAL, "unknown kernel_mode");
+    if (p.kernel_mode == WSP_KERNELS_PLANES && p.precision != WSP_FP32_FP64PHASE)
+        return fail(WSP_EINVAL, "w-plane kernels need precision WSP_FP32_FP64PHASE");
+    if (!(p.plane_dq >= 0.0) || !(p.plane_dw >= 0.0) || !std::isfinite(p.plane_dq) ||
+        !std::isfinite(p.plane_dw) || p.plane_dq > 1.0)
+        return fail(WSP_EINVAL, "plane_dq must be in [0, 1] and plane_dw >= 0 (0 = default)");
 
     Geom g{};
     g.n = p.n;
@@ -272,6 +288,11 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     g.slope = (rho_c / (n_c * g.du)) * p.support_scale;
     g.rows_lo = g.G;  // all grid rows, until a plan narrows them
     g.rows_hi = 0;
+    g.planes = p.kernel_mode == WSP_KERNELS_PLANES;
+    g.plane_dq = p.plane_dq > 0.0 ? p.plane_dq : 1.0 / 64.0;
+    g.plane_dw = p.plane_dw > 0.0 ? p.plane_dw : 1.0 / 16.0;
+    g.plane_inv_dq = 1.0 / g.plane_dq;
+    g.plane_inv_dw = 1.0 / g.plane_dw;
     double xr = 2.0 * M_PI * g.a * g.r_max;
     double ymax = std::fmax(0.25 * g.beta * g.beta, std::fabs(0.25 * (g.beta * g.beta - xr * xr)));
     int terms = (int)std::ceil(2.0 * std::sqrt(ymax)) + 30;
@@ -444,7 +465,8 @@ wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_by
     if (!c) return fail(WSP_EINVAL, "null argument");
     if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
     const size_t cb = cplx_bytes(c);
-    if (kernel_bytes) *kernel_bytes = (size_t)c->plan.total_taps * cb;
+    if (kernel_bytes)
+        *kernel_bytes = c->g.planes ? (size_t)c->plan.table_len * 16 : (size_t)c->plan.total_taps * cb;
     if (grid_bytes) *grid_bytes = (size_t)c->g.G * c->g.G * c->g.n_stacks * cb;
     if (scratch_bytes)
         *scratch_bytes = align256(c->fft_work) + align256(half_bytes(c)) + align256((size_t)c->plan.m * cb) +
@@ -498,7 +520,18 @@ wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void
     if (count <= 0 || first + count > c->plan.m) return fail(WSP_EINVAL, "bad visibility range");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = as_stream(stream);
-    HIP_OR_FAIL(launch_build(c, first, count, s), "build");
+    if (c->g.planes) {
+        // the lattice serves every visibility: built by the first part
+        if (first == 0) {
+            HIP_OR_FAIL(launch_plane_build(c, s), "w-plane build");
+        } else {
+            c->built_upto = first + count;
+            c->built = c->built_upto == c->plan.m;
+            return WSP_OK;
+        }
+    } else {
+        HIP_OR_FAIL(launch_build(c, first, count, s), "build");
+    }
     unsigned long long st[2] = {0, 0};
     HIP_OR_FAIL(hipMemcpyAsync(st, c->plan.stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats");
     HIP_OR_FAIL(hipStreamSynchronize(s), "build");
@@ -573,7 +606,15 @@ wsp_status wsp_kernel_values(wsp_ctx *c, int64_t p, void *out, int32_t *jp, int3
     if (jp) *jp = j;
     if (u0) *u0 = (int32_t)((int64_t)std::floor(uu * c->g.inv_du) - j / 2 + 1);
     if (v0) *v0 = (int32_t)((int64_t)std::floor(vv * c->g.inv_du) - j / 2 + 1);
-    if (out) {
+    if (out && c->g.planes) {
+        void *d = nullptr;
+        const size_t bytes = (size_t)j * j * sizeof(float) * 2;
+        HIP_OR_FAIL(hipMalloc(&d, bytes), "hipMalloc");
+        hipError_t e = run_plane_taps(c, sidx, d, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(out, d, bytes, hipMemcpyDeviceToHost);
+        hipFree(d);
+        if (e != hipSuccess) return hip_fail(e, "w-plane taps");
+    } else if (out) {
         // copy the visibility's block and undo the tile grouping (row-major out)
         const size_t cb = cplx_bytes(c);
         int32_t uw = 0, vw = 0;

@@ -12,6 +12,7 @@
 #include <type_traits>
 
 #include "wsp_devmath.h"
+#include "wsp_plane.h"
 
 namespace wsp {
 
@@ -271,6 +272,11 @@ struct TileArgs {
     int n_items;
     int tile_bits;
     int G;
+    // w-plane mode: per-entry plane records (work-list order) and the lattice
+    const int4 *prec;
+    const float *ptw;
+    const float4 *table;
+    float inv_dq;
 };
 
 // XCD-aware block order: consecutive items (neighbouring tiles) go to the
@@ -380,7 +386,7 @@ __device__ __forceinline__ void for_batches(int kbeg, int kend, F &&f) {
 // entry's tap sub-block, multiply by the staged grid values and reduce; each
 // entry's partial sum goes to dpart[entry] (entries are stored grouped by
 // visibility), summed per visibility by k_degrid_reduce.
-template <bool kFP64>
+template <bool kFP64, bool kPlanes>
 __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
                                                            const typename Types<kFP64>::C *__restrict__ grids,
                                                            typename Types<kFP64>::C *dpart, TileArgs t) {
@@ -389,7 +395,9 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
     __shared__ C tile[kTile * kTile];
     __shared__ int s_geo[kChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int s_idx[kChunk];
-    __shared__ int64_t s_off[kChunk];
+    __shared__ int64_t s_off[kPlanes ? 1 : kChunk];
+    __shared__ int4 s_prec[kPlanes ? kChunk : 1];
+    __shared__ float s_sw[kPlanes ? kChunk : 1];
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     {
@@ -407,14 +415,22 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
             const int4 rec = t.wrec[base + q];
             s_geo[q] = rec.z;
             s_idx[q] = t.ent_sorted[base + q];
-            s_off[q] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            if constexpr (kPlanes) {
+                s_prec[q] = t.prec[base + q];
+                s_sw[q] = t.ptw[base + q];
+            } else {
+                s_off[q] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            }
         }
         __syncthreads();
         for (int j = wid; j < n; j += kWaves) {
             const int geo = s_geo[j];
             const int nc = geo & 255, nr = (geo >> 8) & 255;
             const int lx0 = (geo >> 16) & 255, ly0 = (geo >> 24) & 255;
-            const C *tp = taps + s_off[j];
+            const C *tp = taps;
+            PlaneEntry pe{};
+            if constexpr (kPlanes) pe = plane_entry(s_prec[j], s_sw[j], t.table);
+            else tp = taps + s_off[j];
             const float inv_nc = recip_nc(nc);
             const int ntap = nr * nc;
             const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
@@ -423,16 +439,23 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
                 constexpr int U = decltype(ucount)::value;
                 C K[U];
                 int li[U];
+                PlaneLoad L[kPlanes ? U : 1];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     // past the sub-block: re-read tap 0 and weight it by zero below
                     const int k = k0 + 64 * u + lane < ntap ? k0 + 64 * u + lane : 0;
                     const int row = sub_row(k, inv_nc);
                     li[u] = sub_cell(cell0, k, row, nc);
-                    K[u] = load_tap(&tp[k]);  // the sub-block is contiguous, row-major
+                    if constexpr (kPlanes) L[u] = plane_load(pe, row, k - (int)__umul24((unsigned)row, (unsigned)nc), t.inv_dq);
+                    else K[u] = load_tap(&tp[k]);  // the sub-block is contiguous, row-major
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
+                    if constexpr (kPlanes) {
+                        const float2 v = plane_value(L[u], pe.sw, pe.sgn);
+                        K[u].x = v.x;
+                        K[u].y = v.y;
+                    }
                     const bool ok = k0 + 64 * u + lane < ntap;
                     const C z = tile[li[u]];
                     const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
@@ -457,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
 // entries per pass instead of spreading one entry over 64 lanes.  Otherwise
 // as k_degrid_tiles.
 constexpr int kGroup = 16;
-template <bool kFP64>
+template <bool kFP64, bool kPlanes>
 __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<kFP64>::C *__restrict__ taps,
                                                            const typename Types<kFP64>::C *__restrict__ grids,
                                                            typename Types<kFP64>::C *dpart, TileArgs t) {
@@ -468,7 +491,9 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
     __shared__ C tile[kTile * kTile];
     __shared__ int s_geo[kChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int s_idx[kChunk];
-    __shared__ int64_t s_off[kChunk];
+    __shared__ int64_t s_off[kPlanes ? 1 : kChunk];
+    __shared__ int4 s_prec[kPlanes ? kChunk : 1];
+    __shared__ float s_sw[kPlanes ? kChunk : 1];
     const int item = xcd_item(blockIdx.x, t.n_items);
     if (item >= t.n_items) return;  // uniform over the block
     {
@@ -487,7 +512,12 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
             const int4 rec = t.wrec[base + q];
             s_geo[q] = rec.z;
             s_idx[q] = t.ent_sorted[base + q];
-            s_off[q] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            if constexpr (kPlanes) {
+                s_prec[q] = t.prec[base + q];
+                s_sw[q] = t.ptw[base + q];
+            } else {
+                s_off[q] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            }
         }
         __syncthreads();
         for (int j0 = wid * kPer; j0 < n; j0 += kWaves * kPer) {
@@ -496,7 +526,10 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
             const int geo = s_geo[valid ? j : j0];
             const int nc = geo & 255, nr = (geo >> 8) & 255;
             const int lx0 = (geo >> 16) & 255, ly0 = (geo >> 24) & 255;
-            const C *tp = taps + s_off[valid ? j : j0];
+            const C *tp = taps;
+            PlaneEntry pe{};
+            if constexpr (kPlanes) pe = plane_entry(s_prec[valid ? j : j0], s_sw[valid ? j : j0], t.table);
+            else tp = taps + s_off[valid ? j : j0];
             const float inv_nc = recip_nc(nc);
             const int ntap = valid ? nr * nc : 0;
             const int cell0 = ly0 * kTile + lx0;
@@ -504,23 +537,33 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
             for (int k0 = 0; __any(k0 < ntap); k0 += kGroup * kU) {
                 C K[kU];
                 int li[kU];
+                PlaneLoad L[kPlanes ? kU : 1];
                 // slots past every group's entry are skipped (uniform), lanes past
                 // their own entry load nothing and add zero
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     K[u].x = 0;
                     K[u].y = 0;
+                    if constexpr (kPlanes) L[u] = plane_zero();
                     li[u] = cell0;
                     const bool ok = k0 + kGroup * u + gl < ntap;
                     if (__any(ok)) {
                         const int k = ok ? k0 + kGroup * u + gl : 0;
                         const int row = sub_row(k, inv_nc);
                         li[u] = sub_cell(cell0, k, row, nc);
-                        if (ok) K[u] = load_tap(&tp[k]);
+                        if (ok) {
+                            if constexpr (kPlanes) L[u] = plane_load(pe, row, k - (int)__umul24((unsigned)row, (unsigned)nc), t.inv_dq);
+                            else K[u] = load_tap(&tp[k]);
+                        }
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
+                    if constexpr (kPlanes) {
+                        const float2 v = plane_value(L[u], pe.sw, pe.sgn);
+                        K[u].x = v.x;
+                        K[u].y = v.y;
+                    }
                     const bool ok = k0 + kGroup * u + gl < ntap;
                     const C z = tile[li[u]];
                     const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
@@ -576,7 +619,7 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
 // and a wavefront's LDS accesses complete in order, so plain read-modify-
 // write is exact.  The tile is then stored into the grid (the tile's only
 // item) or into a partial-tile slot that k_reduce_tiles sums in item order.
-template <bool kFP64, int kH>
+template <bool kFP64, int kH, bool kPlanes>
 __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(const typename Types<kFP64>::C *__restrict__ taps,
                                                          const typename Types<kFP64>::C *__restrict__ yw,
                                                          typename Types<kFP64>::C *grids, TileArgs t) {
@@ -584,7 +627,9 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
     constexpr int kRows = kTile / kH;  // tile rows of this block
     __shared__ C tile[kRows * kTile + 1];  // + a spare cell for lanes without a tap
     __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
-    __shared__ int64_t s_off[kGChunk];
+    __shared__ int64_t s_off[kPlanes ? 1 : kGChunk];
+    __shared__ int4 s_prec[kPlanes ? kGChunk : 1];
+    __shared__ float s_sw[kPlanes ? kGChunk : 1];
     __shared__ C s_y[kGChunk];
     static_assert(kGChunk <= kThreads / kH, "one thread stages one entry");
     int part;
@@ -604,7 +649,12 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
         if ((int)threadIdx.x < n) {
             const int4 rec = t.wrec[base + threadIdx.x];
             s_geo[threadIdx.x] = rec.z;
-            s_off[threadIdx.x] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            if constexpr (kPlanes) {
+                s_prec[threadIdx.x] = t.prec[base + threadIdx.x];
+                s_sw[threadIdx.x] = t.ptw[base + threadIdx.x];
+            } else {
+                s_off[threadIdx.x] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            }
             s_y[threadIdx.x] = yw[rec.w];
         }
         __syncthreads();
@@ -615,10 +665,17 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
             const int jl = j0 + lane;
             int geo_l = 0;
             int64_t off_l = 0;
+            int4 prec_l = make_int4(0, 0, 0, 0);
+            float sw_l = 0.0f;
             C y_l = zero;
             if (jl < n) {
                 geo_l = s_geo[jl];
-                off_l = s_off[jl];
+                if constexpr (kPlanes) {
+                    prec_l = s_prec[jl];
+                    sw_l = s_sw[jl];
+                } else {
+                    off_l = s_off[jl];
+                }
                 y_l = s_y[jl];
             }
             const int nr_l = (geo_l >> 8) & 255, ly0_l = (geo_l >> 24) & 255;
@@ -627,8 +684,18 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                 const int l = __builtin_ctzll(hits);
                 hits &= hits - 1;
                 const int ez = __builtin_amdgcn_readlane(geo_l, l);
-                const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
+                int64_t off = 0;
+                PlaneEntry pe{};
+                if constexpr (kPlanes) {
+                    const int4 pr = make_int4(__builtin_amdgcn_readlane(prec_l.x, l),
+                                              __builtin_amdgcn_readlane(prec_l.y, l),
+                                              __builtin_amdgcn_readlane(prec_l.z, l),
+                                              __builtin_amdgcn_readlane(prec_l.w, l));
+                    pe = plane_entry(pr, bcast(sw_l, l), t.table);
+                } else {
+                    off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
+                }
                 C y;
                 y.x = bcast(y_l.x, l);
                 y.y = bcast(y_l.y, l);
@@ -644,6 +711,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                     constexpr int U = decltype(ucount)::value;
                     C K[U], z[U];
                     int li[U];
+                    PlaneLoad L[kPlanes ? U : 1];
                     // past the run: re-read its first tap and add zero to the spare cell
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
@@ -651,7 +719,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                         const int k = ok ? k0 + 64 * u + lane : kbeg;
                         const int row = sub_row(k, inv_nc);
                         li[u] = ok ? sub_cell(cell0, k, row, nc) : kRows * kTile;
-                        K[u] = load_tap(&tp[k]);
+                        if constexpr (kPlanes) L[u] = plane_load(pe, row, k - (int)__umul24((unsigned)row, (unsigned)nc), t.inv_dq);
+                        else K[u] = load_tap(&tp[k]);
                     }
                     // all reads before all writes: the cells of the U x 64 taps are
                     // distinct (only the spare cell repeats)
@@ -659,6 +728,11 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                     for (int u = 0; u < U; ++u) z[u] = tile[li[u]];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
+                        if constexpr (kPlanes) {
+                            const float2 v = plane_value(L[u], pe.sw, pe.sgn);
+                            K[u].x = v.x;
+                            K[u].y = v.y;
+                        }
                         const bool ok = k0 + 64 * u + lane < kend;
                         using R = decltype(K[u].x);
                         const R kr = ok ? K[u].x : (R)0, ki = ok ? K[u].y : (R)0;
@@ -693,7 +767,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
 // runs) are issued together; then the slots are added into the tile one
 // after the other, in entry order (two entries may share cells).
 constexpr int kSlots = 8;
-template <bool kFP64, int kH>
+template <bool kFP64, int kH, bool kPlanes>
 __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(const typename Types<kFP64>::C *__restrict__ taps,
                                                                         const typename Types<kFP64>::C *__restrict__ yw,
                                                                         typename Types<kFP64>::C *grids, TileArgs t) {
@@ -701,7 +775,9 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
     constexpr int kRows = kTile / kH;  // tile rows of this block
     __shared__ C tile[kRows * kTile + 1];  // + a spare cell for lanes without a tap
     __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
-    __shared__ int64_t s_off[kGChunk];
+    __shared__ int64_t s_off[kPlanes ? 1 : kGChunk];
+    __shared__ int4 s_prec[kPlanes ? kGChunk : 1];
+    __shared__ float s_sw[kPlanes ? kGChunk : 1];
     __shared__ C s_y[kGChunk];
     int part;
     const int item = xcd_item_part(blockIdx.x, t.n_items, kH, &part);
@@ -720,7 +796,12 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
         if ((int)threadIdx.x < n) {
             const int4 rec = t.wrec[base + threadIdx.x];
             s_geo[threadIdx.x] = rec.z;
-            s_off[threadIdx.x] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            if constexpr (kPlanes) {
+                s_prec[threadIdx.x] = t.prec[base + threadIdx.x];
+                s_sw[threadIdx.x] = t.ptw[base + threadIdx.x];
+            } else {
+                s_off[threadIdx.x] = ((int64_t)rec.y << 32) | (uint32_t)rec.x;
+            }
             s_y[threadIdx.x] = yw[rec.w];
         }
         __syncthreads();
@@ -728,10 +809,17 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
             const int jl = j0 + lane;
             int geo_l = 0;
             int64_t off_l = 0;
+            int4 prec_l = make_int4(0, 0, 0, 0);
+            float sw_l = 0.0f;
             C y_l = zero;
             if (jl < n) {
                 geo_l = s_geo[jl];
-                off_l = s_off[jl];
+                if constexpr (kPlanes) {
+                    prec_l = s_prec[jl];
+                    sw_l = s_sw[jl];
+                } else {
+                    off_l = s_off[jl];
+                }
                 y_l = s_y[jl];
             }
             const int nr_l = (geo_l >> 8) & 255, ly0_l = (geo_l >> 24) & 255;
@@ -739,11 +827,14 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
             // current run (uniform): taps [k0, kend) of the entry's rows in the
             // band; the entry's y sits in lane yl of y_l
             const C *tp = taps;
+            PlaneEntry pe{};
             int k0 = 0, kend = 0, kbeg = 0, nc = 1, cell0 = 0, yl = 0;
             float inv_nc = 1.0f;
             while (hits || k0 < kend) {
                 C K[kSlots];
                 int li[kSlots], ys[kSlots];
+                PlaneLoad L[kPlanes ? kSlots : 1];
+                float sws[kPlanes ? kSlots : 1], sgs[kPlanes ? kSlots : 1];
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
                     li[sl] = kRows * kTile;  // lanes without a tap update the spare cell by zero
@@ -751,14 +842,22 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                         const int l = __builtin_ctzll(hits);
                         hits &= hits - 1;
                         const int ez = __builtin_amdgcn_readlane(geo_l, l);
-                        const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
-                                            (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
+                        if constexpr (kPlanes) {
+                            const int4 pr = make_int4(__builtin_amdgcn_readlane(prec_l.x, l),
+                                                      __builtin_amdgcn_readlane(prec_l.y, l),
+                                                      __builtin_amdgcn_readlane(prec_l.z, l),
+                                                      __builtin_amdgcn_readlane(prec_l.w, l));
+                            pe = plane_entry(pr, bcast(sw_l, l), t.table);
+                        } else {
+                            const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(off_l >> 32), l) << 32) |
+                                                (uint32_t)__builtin_amdgcn_readlane((int)off_l, l);
+                            tp = taps + off;
+                        }
                         yl = l;
                         const int nr = (ez >> 8) & 255, ly0 = (ez >> 24) & 255;
                         const int lo = ly0 > band0 ? ly0 : band0;
                         const int hi = (ly0 + nr < band0 + kBand) ? ly0 + nr : band0 + kBand;
                         nc = ez & 255;
-                        tp = taps + off;
                         kbeg = (lo - ly0) * nc;
                         kend = (hi - ly0) * nc;
                         k0 = kbeg;
@@ -767,17 +866,28 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                     }
                     K[sl] = zero;
                     ys[sl] = yl;
+                    if constexpr (kPlanes) {
+                        L[sl] = plane_zero();
+                        sws[sl] = pe.sw;
+                        sgs[sl] = pe.sgn;
+                    }
                     if (k0 < kend) {  // uniform: this slot takes taps [k0, k0 + 64) of the run
                         const bool ok = k0 + lane < kend;
                         const int k = ok ? k0 + lane : kbeg;
                         const int row = sub_row(k, inv_nc);
                         li[sl] = ok ? sub_cell(cell0, k, row, nc) : kRows * kTile;  // else: the spare cell
-                        K[sl] = load_tap(&tp[k]);
+                        if constexpr (kPlanes) L[sl] = plane_load(pe, row, k - (int)__umul24((unsigned)row, (unsigned)nc), t.inv_dq);
+                        else K[sl] = load_tap(&tp[k]);
                         k0 += 64;
                     }
                 }
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
+                    if constexpr (kPlanes) {
+                        const float2 v = plane_value(L[sl], sws[sl], sgs[sl]);
+                        K[sl].x = v.x;
+                        K[sl].y = v.y;
+                    }
                     const auto yx = bcast(y_l.x, ys[sl]), yy = bcast(y_l.y, ys[sl]);
                     const C z = tile[li[sl]];
                     C o;
@@ -909,6 +1019,33 @@ hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
     return hipSuccess;
 }
 
+void set_plane_args(const wsp_ctx *c, TileArgs *ta) {
+    if (!c->g.planes) return;
+    ta->prec = c->plan.prec;
+    ta->ptw = c->plan.ptw;
+    ta->table = (const float4 *)c->taps;
+    ta->inv_dq = (float)c->g.plane_inv_dq;
+}
+
+// w-plane mode test hook: the J_p x J_p taps of sorted visibility sidx,
+// row-major, interpolated exactly as the tile kernels do (the sub-block is
+// the whole support).
+__global__ void k_plane_vis_taps(const double *__restrict__ ux, const double *__restrict__ vx,
+                                 const double *__restrict__ weff, const int32_t *__restrict__ jp,
+                                 const int64_t *__restrict__ plane_off, int n_pairs, double inv_dw,
+                                 const float4 *__restrict__ table, float inv_dq, int64_t sidx,
+                                 float2 *out) {
+    const int J = jp[sidx];
+    int4 rec;
+    float sw;
+    plane_record(weff[sidx], ux[sidx], vx[sidx], plane_off, n_pairs, inv_dw, &rec, &sw);
+    const PlaneEntry pe = plane_entry(rec, sw, table);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < J * J; t += gridDim.x * blockDim.x) {
+        const int row = t / J, col = t - row * J;
+        out[t] = plane_value(plane_load(pe, row, col, inv_dq), pe.sw, pe.sgn);
+    }
+}
+
 template <bool kFP64>
 hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_centres,
                     hipStream_t s) {
@@ -929,16 +1066,25 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     const Plan &pl = c->plan;
     TileArgs ta{pl.wrec,      pl.ent_sorted,   pl.item_start, pl.item_key, pl.item_sole,
                 pl.item_slot, c->scratch_part, pl.n_items,    pl.tile_bits, g.G};
+    set_plane_args(c, &ta);
     ev = stage_begin(c, s);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
         // entries of a few tens of taps (many w-stacks) go four to a wavefront
-        if (pl.total_taps < kSmallEntryTaps * pl.n_entries) {
-            hipLaunchKernelGGL(k_degrid_small<kFP64>, dim3(nb), dim3(kThreads), 0, s,
-                               (const C *)c->taps, (const C *)c->grids, (C *)c->scratch_dpart, ta);
-        } else {
-            hipLaunchKernelGGL(k_degrid_tiles<kFP64>, dim3(nb), dim3(kThreads), 0, s, (const C *)c->taps,
-                               (const C *)c->grids, (C *)c->scratch_dpart, ta);
+        const bool small = pl.total_taps < kSmallEntryTaps * pl.n_entries;
+        const C *tp = (const C *)c->taps;
+        const C *gr = (const C *)c->grids;
+        C *dp = (C *)c->scratch_dpart;
+        if constexpr (!kFP64) {
+            if (g.planes) {
+                if (small) hipLaunchKernelGGL((k_degrid_small<false, true>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
+                else hipLaunchKernelGGL((k_degrid_tiles<false, true>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
+                nb = 0;
+            }
+        }
+        if (nb > 0) {
+            if (small) hipLaunchKernelGGL((k_degrid_small<kFP64, false>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
+            else hipLaunchKernelGGL((k_degrid_tiles<kFP64, false>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
         }
     }
     hipLaunchKernelGGL(k_degrid_reduce<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s,
@@ -964,16 +1110,25 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     ev = stage_begin(c, s);
     hipLaunchKernelGGL(k_prep_vis<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)vis,
                        (C *)c->scratch_yw, a);
+    set_plane_args(c, &ta);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        if (pl.total_taps < kSmallEntryTaps * pl.n_entries) {
-            hipLaunchKernelGGL((k_grid_small<kFP64, kGridSplitSmall>), dim3(kGridSplitSmall * nb),
-                               dim3(kThreads / kGridSplitSmall), 0, s, (const C *)c->taps,
-                               (const C *)c->scratch_yw, (C *)c->grids, ta);
-        } else {
-            hipLaunchKernelGGL((k_grid_tiles<kFP64, kGridSplit>), dim3(kGridSplit * nb),
-                               dim3(kThreads / kGridSplit), 0, s, (const C *)c->taps,
-                               (const C *)c->scratch_yw, (C *)c->grids, ta);
+        const bool small = pl.total_taps < kSmallEntryTaps * pl.n_entries;
+        const C *tp = (const C *)c->taps;
+        const C *yw = (const C *)c->scratch_yw;
+        C *gr = (C *)c->grids;
+        const dim3 gs(kGridSplitSmall * nb), bs(kThreads / kGridSplitSmall);
+        const dim3 gt(kGridSplit * nb), bt(kThreads / kGridSplit);
+        if constexpr (!kFP64) {
+            if (g.planes) {
+                if (small) hipLaunchKernelGGL((k_grid_small<false, kGridSplitSmall, true>), gs, bs, 0, s, tp, yw, gr, ta);
+                else hipLaunchKernelGGL((k_grid_tiles<false, kGridSplit, true>), gt, bt, 0, s, tp, yw, gr, ta);
+                nb = 0;
+            }
+        }
+        if (nb > 0) {
+            if (small) hipLaunchKernelGGL((k_grid_small<kFP64, kGridSplitSmall, false>), gs, bs, 0, s, tp, yw, gr, ta);
+            else hipLaunchKernelGGL((k_grid_tiles<kFP64, kGridSplit, false>), gt, bt, 0, s, tp, yw, gr, ta);
         }
     }
     if (pl.n_mtiles > 0) {
@@ -1004,6 +1159,14 @@ hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s) {
 hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s) {
     if (c->p.precision == WSP_FP64) return grid_t<true>(c, vis, image, c->plan_centres, s);
     return grid_t<false>(c, vis, image, c->plan_centres, s);
+}
+
+hipError_t run_plane_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s) {
+    const Plan &pl = c->plan;
+    hipLaunchKernelGGL(k_plane_vis_taps, dim3(64), dim3(256), 0, s, pl.ux, pl.vx, pl.weff, pl.jp,
+                       pl.plane_off, pl.n_pairs, c->g.plane_inv_dw, (const float4 *)c->taps,
+                       (float)c->g.plane_inv_dq, sidx, (float2 *)out_dev);
+    return hipGetLastError();
 }
 
 }  // namespace wsp

@@ -70,6 +70,12 @@ __device__ __forceinline__ PointSet point_set(double ux, double vx, int jp) {
 }
 
 struct BuildArgs {
+    // w-plane mode (plane_off != null): "visibility" j is the plane |w| = j dw,
+    // its points the samples q = i dq, written into the pair rows j and j - 1
+    const int64_t *plane_off;
+    int n_pairs;
+    double plane_dq, plane_dw;
+    float2 *table2;
     const int32_t *border;
     int64_t m;
     const double *ux, *vx, *weff;
@@ -82,6 +88,29 @@ struct BuildArgs {
     int max_panels;
     unsigned long long *stats;
 };
+
+// Samples of plane j: as many as the pair row that reads the most of them
+// (row j, or row j - 1 for the last plane; rows grow with j).
+__device__ __forceinline__ PointSet plane_points(const BuildArgs &A, int j) {
+    const int r = j < A.n_pairs ? j : A.n_pairs - 1;
+    const int64_t n = A.plane_off[r + 1] - A.plane_off[r];
+    return {(double)(n - 1) * A.plane_dq, n, true};
+}
+
+// Visibility (or plane) of build slot b, its w_eff and quadrature points.
+struct Target {
+    int p;
+    double weff;
+    PointSet ps;
+};
+__device__ __forceinline__ Target build_target(const BuildArgs &A, int64_t b) {
+    if (A.plane_off) {
+        const int j = (int)b;
+        return {j, (double)j * A.plane_dw, plane_points(A, j)};
+    }
+    const int p = A.border[b];
+    return {p, A.weff[p], point_set(A.ux[p], A.vx[p], A.jp[p])};
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -289,10 +318,8 @@ __global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, 
     const int wid = threadIdx.x / kWave;
     const int i = blockIdx.x * kWavesPerBlock + wid;
     if (i >= nb) return;  // whole wave leaves; no block-wide barriers below
-    const int p = A.border[batch0 + i];
-    const double ux = A.ux[p], vx = A.vx[p], weff = A.weff[p];
-    const int jp = A.jp[p];
-    const double qmax = point_set(ux, vx, jp).qmax;
+    const Target tg = build_target(A, batch0 + i);
+    const double weff = tg.weff, qmax = tg.ps.qmax;
     float *bnd = nullptr;
     bool capped = false;
     int P = adaptive_partition(s_bnd[wid][0], s_bnd[wid][1], &bnd, weff, qmax, A, lane, &capped);
@@ -327,13 +354,15 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         else hi = mid - 1;
     }
     const int i = lo;
-    const int p = A.border[batch0 + i];
     const Geom &g = A.g;
-    const double ux = A.ux[p], vx = A.vx[p], weff = A.weff[p];
-    const int jp = A.jp[p];
-    const int64_t off = A.tap_off[p];
-    const PointSet ps = point_set(ux, vx, jp);
+    const Target tg = build_target(A, batch0 + i);
+    const int p = tg.p;
+    const bool planes = A.plane_off != nullptr;
+    const double ux = planes ? 0.0 : A.ux[p], vx = planes ? 0.0 : A.vx[p], weff = tg.weff;
+    const int jp = planes ? 1 : A.jp[p];
+    const PointSet ps = tg.ps;
     const int64_t ntap = ps.npts;
+    const double sstep = planes ? A.plane_dq : kSampleStep;
     const int P = npan[i];
     const float *bnd = part + (int64_t)i * (kMaxPanels + 2);
     const int64_t chunk = (int64_t)kWave * kTapsPerLane;
@@ -349,7 +378,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         int row = (int)(t / jp);
         int col = (int)(t - (int64_t)row * jp);
         double du = ux - (double)col, dv = vx - (double)row;
-        q[k] = (t < ntap) ? (ps.sampled ? (double)t * kSampleStep : sqrt(du * du + dv * dv)) : 0.0;
+        q[k] = (t < ntap) ? (ps.sampled ? (double)t * sstep : sqrt(du * du + dv * dv)) : 0.0;
         qf[k] = (float)(kTwoPi * q[k]);
         // per-tap factors of 8 / x and sqrt(2 / (pi x)) (unused when q = 0)
         qinv[k] = q[k] > 0.0 ? (float)(1.0 / q[k]) : 0.0f;
@@ -435,6 +464,19 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
             }
         }
     }
+    if (planes) {
+        // sample t of plane j: T[j, t] of pair row j and T[j, t] of row j - 1
+        const int64_t n_lo = p < A.n_pairs ? A.plane_off[p + 1] - A.plane_off[p] : 0;
+        const int64_t n_hi = p >= 1 ? A.plane_off[p] - A.plane_off[p - 1] : 0;
+#pragma unroll
+        for (int k = 0; k < kTapsPerLane; ++k) {
+            const int64_t t = cbase + (int64_t)k * kWave + lane;
+            const float2 v = make_float2((float)accr[k], (float)acci[k]);
+            if (t < n_lo) A.table2[2 * (A.plane_off[p] + t)] = v;
+            if (t < n_hi) A.table2[2 * (A.plane_off[p - 1] + t) + 1] = v;
+        }
+        return;
+    }
     if (ps.sampled) {
         double2 *dst = samples + samp_off[i];
 #pragma unroll
@@ -444,6 +486,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         }
         return;
     }
+    const int64_t off = A.tap_off[p];
     const int u0w = A.u0w[p], v0w = A.v0w[p];
 #pragma unroll
     for (int k = 0; k < kTapsPerLane; ++k) {
@@ -519,31 +562,18 @@ __global__ void k_unit_counts(BuildArgs A, int64_t batch0, int nb, int64_t chunk
         scnt[i] = 0;
         return;
     }
-    const int p = A.border[batch0 + i];
-    const PointSet ps = point_set(A.ux[p], A.vx[p], A.jp[p]);
+    const PointSet ps = build_target(A, batch0 + i).ps;
     cnt[i] = (int)((ps.npts + chunk - 1) / chunk);
-    scnt[i] = ps.sampled ? ps.npts : 0;
+    scnt[i] = (ps.sampled && !A.plane_off) ? ps.npts : 0;  // plane samples go to the lattice
 }
 
 }  // namespace
 
-hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s) {
-    BuildArgs A{};
+namespace {
+
+// Phases 1 and 2 over build slots first .. first + count - 1, in batches.
+hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t count, hipStream_t s) {
     const Plan &pl = c->plan;
-    A.border = pl.border;
-    A.m = pl.m;
-    A.ux = pl.ux;
-    A.vx = pl.vx;
-    A.weff = pl.weff;
-    A.jp = pl.jp;
-    A.u0w = pl.u0w;
-    A.v0w = pl.v0w;
-    A.tap_off = pl.tap_off;
-    A.taps = c->taps;
-    A.g = c->g;
-    A.tol = c->p.quad_abs_tol > 0.0 ? c->p.quad_abs_tol : c->p.quad_rel_tol;
-    A.max_panels = c->p.quad_max_panels;
-    A.stats = pl.stats;
     hipError_t e = hipSuccess;
     if (first == 0) {
         e = hipMemsetAsync(pl.stats, 0, 2 * sizeof(unsigned long long), s);
@@ -633,6 +663,45 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s)
     cleanup();
     return hipSuccess;
 #undef WSP_BSTEP
+}
+
+BuildArgs common_args(wsp_ctx *c) {
+    BuildArgs A{};
+    A.g = c->g;
+    A.tol = c->p.quad_abs_tol > 0.0 ? c->p.quad_abs_tol : c->p.quad_rel_tol;
+    A.max_panels = c->p.quad_max_panels;
+    A.stats = c->plan.stats;
+    return A;
+}
+
+}  // namespace
+
+hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s) {
+    BuildArgs A = common_args(c);
+    const Plan &pl = c->plan;
+    A.border = pl.border;
+    A.m = pl.m;
+    A.ux = pl.ux;
+    A.vx = pl.vx;
+    A.weff = pl.weff;
+    A.jp = pl.jp;
+    A.u0w = pl.u0w;
+    A.v0w = pl.v0w;
+    A.tap_off = pl.tap_off;
+    A.taps = c->taps;
+    return run_build(c, A, first, count, s);
+}
+
+// The w-plane lattice: planes j = 0 .. n_pairs (|w| = j dw), FP32 quadrature path.
+hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s) {
+    BuildArgs A = common_args(c);
+    const Plan &pl = c->plan;
+    A.plane_off = pl.plane_off;
+    A.n_pairs = pl.n_pairs;
+    A.plane_dq = c->g.plane_dq;
+    A.plane_dw = c->g.plane_dw;
+    A.table2 = (float2 *)c->taps;
+    return run_build(c, A, 0, (int64_t)pl.n_pairs + 1, s);
 }
 
 }  // namespace wsp

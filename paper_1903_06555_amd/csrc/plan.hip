@@ -4,9 +4,11 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
+#include <cstring>
 #include <limits>
 
 #include "wsp_internal.h"
+#include "wsp_plane.h"
 
 namespace wsp {
 
@@ -437,6 +439,106 @@ void free_sorted_plan(Plan &pl) {
     hipFree(pl.mt_first);
     pl.item_slot = pl.mt_first = nullptr;
     pl.n_multi = pl.n_mtiles = 0;
+    hipFree(pl.plane_off);
+    hipFree(pl.prec);
+    hipFree(pl.ptw);
+    pl.plane_off = nullptr;
+    pl.prec = nullptr;
+    pl.ptw = nullptr;
+    pl.n_pairs = 0;
+    pl.table_len = 0;
+}
+
+// ---- w-plane mode ---------------------------------------------------------------
+
+// max |w_eff| as the bit pattern of a non-negative double (ordered like the value)
+__global__ void k_absmax_weff(const double *__restrict__ weff, int64_t m, unsigned long long *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (i < m) v = (unsigned long long)__double_as_longlong(fabs(weff[i]));
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+}
+
+// Per entry (work-list order): the pair row of its visibility's |w_eff|, the
+// w weight, the conjugation flag and the visibility's offset from the
+// entry's first tap.
+__global__ void k_plane_records(const int32_t *__restrict__ idx_sorted, const int4 *__restrict__ ent,
+                                const double *__restrict__ ux, const double *__restrict__ vx,
+                                const double *__restrict__ weff, const int64_t *__restrict__ plane_off,
+                                int n_pairs, double inv_dw, int64_t E, int4 *prec, float *ptw) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= E) return;
+    const int4 en = ent[idx_sorted[s]];
+    const int p = en.x;
+    const int c0 = en.y & 0xFFFF, r0 = (en.y >> 16) & 0xFFFF;
+    plane_record(weff[p], ux[p] - (double)c0, vx[p] - (double)r0, plane_off, n_pairs, inv_dw,
+                 &prec[s], &ptw[s]);
+}
+
+// Lattice layout for the planned visibilities (host arithmetic in FP64) and
+// the per-entry plane records.  Pair row j serves |w_eff| in [j dw, (j + 1) dw):
+// its supports are at most J_p((j + 1) dw), whose taps lie within
+// J_p / sqrt(2) cells of the visibility.
+hipError_t plane_setup(wsp_ctx *c, hipStream_t s, bool *too_large) {
+    Plan &pl = c->plan;
+    const Geom &g = c->g;
+    *too_large = false;
+    unsigned long long *d_max = nullptr;
+    hipError_t e = dalloc(&d_max, 1);
+    if (e != hipSuccess) return e;
+    unsigned long long h_max = 0;
+    e = hipMemsetAsync(d_max, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_absmax_weff, dim3(grid1d(pl.m, 256)), dim3(256), 0, s, pl.weff, pl.m, d_max);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_max, d_max, sizeof(h_max), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(d_max);
+    if (e != hipSuccess) return e;
+    double wmax;
+    static_assert(sizeof(wmax) == sizeof(h_max), "bit pattern");
+    memcpy(&wmax, &h_max, sizeof(wmax));
+    const double npairs_d = floor(wmax * g.plane_inv_dw) + 1.0;
+    if (!(npairs_d < 1.0e7)) {
+        *too_large = true;
+        return hipSuccess;
+    }
+    const int n_pairs = (int)npairs_d;
+    std::vector<int64_t> off((size_t)n_pairs + 1);
+    int64_t tot = 0;
+    for (int j = 0; j < n_pairs; ++j) {
+        off[j] = tot;
+        const double w_hi = (double)(j + 1) * c->g.plane_dw * (1.0 + 1e-12) + 1e-12;
+        double jp = (double)g.J + 2.0 * ceil(w_hi * g.slope);
+        if (jp > (double)c->p.max_support) jp = (double)c->p.max_support;
+        tot += (int64_t)floor(jp * 0.70710678118654757 * g.plane_inv_dq) + 3;
+    }
+    off[n_pairs] = tot;
+    if (tot >= (int64_t)0x7FFFFFF0) {  // row offsets are stored as int32
+        *too_large = true;
+        return hipSuccess;
+    }
+    pl.n_pairs = n_pairs;
+    pl.table_len = tot;
+    e = dalloc(&pl.plane_off, (size_t)n_pairs + 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl.plane_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, s);
+    const int64_t E = pl.n_entries;
+    if (e == hipSuccess) e = dalloc(&pl.prec, (size_t)(E > 0 ? E : 1));
+    if (e == hipSuccess) e = dalloc(&pl.ptw, (size_t)(E > 0 ? E : 1));
+    if (e == hipSuccess && E > 0) {
+        hipLaunchKernelGGL(k_plane_records, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent_sorted, pl.ent,
+                           pl.ux, pl.vx, pl.weff, pl.plane_off, n_pairs, g.plane_inv_dw, E, pl.prec,
+                           pl.ptw);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // off[] is released on return
+    return e;
 }
 
 // Tile work lists of the sorted visibilities (see k_entry_fill).

@@ -39,6 +39,10 @@ struct Geom {
     // every stack (rows_lo = G, rows_hi = 0 when the pruning does not pay)
     int rows_lo;
     int rows_hi;
+    // w-plane mode (kernels interpolated from the lattice K(i dq, j dw))
+    bool planes;
+    double plane_dq, plane_inv_dq;
+    double plane_dw, plane_inv_dw;
 };
 
 __host__ __device__ inline bool row_used(int V, const Geom &g) {
@@ -111,6 +115,16 @@ struct Plan {
     int n_mtiles = 0;             // tiles split over several items
     int32_t *mt_first = nullptr;  // [n_mtiles + 1] first item of each split tile (+ n_items)
     int tile_bits = 0;
+    // w-plane mode.  Pair row j (j < n_pairs) holds float4 (T[j, i], T[j+1, i])
+    // for i < plane_off[j + 1] - plane_off[j]; a visibility with
+    // j dw <= |w_eff| < (j + 1) dw reads row j.
+    int n_pairs = 0;
+    int64_t table_len = 0;        // float4 elements of the lattice
+    int64_t *plane_off = nullptr; // [n_pairs + 1] device
+    int4 *prec = nullptr;         // [n_entries] in work-list order: {first float4 of the pair row,
+                                  // last usable i | conj << 31, dx0 bits, dy0 bits}; (dx0, dy0) is
+                                  // the visibility's offset from the entry's first tap
+    float *ptw = nullptr;         // [n_entries] in work-list order: w weight s of the upper plane
 };
 
 // Stages timed with HIP events when timing is enabled (wsp_set_timing).
@@ -179,8 +193,11 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K,
 hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err);
 void free_sorted_plan(Plan &pl);
 
+hipError_t plane_setup(wsp_ctx *c, hipStream_t s, bool *too_large);
+
 // build.hip
 hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s);
+hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s);
 
 // api.cpp: stage timing around one launch (no-ops when timing is off)
 hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);
@@ -189,5 +206,6 @@ void stage_end(wsp_ctx *c, int stage, hipEvent_t start, hipStream_t s);
 // apply.hip
 hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s);
 hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s);
+hipError_t run_plane_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s);
 
 }  // namespace wsp

@@ -32,6 +32,9 @@ WSP_FP32_FP64PHASE = 0
 WSP_FP64 = 1
 
 PRECISIONS = {"fp32_fp64phase": WSP_FP32_FP64PHASE, "fp64": WSP_FP64}
+WSP_KERNELS_EXACT = 0
+WSP_KERNELS_PLANES = 1
+KERNEL_MODES = {"exact": WSP_KERNELS_EXACT, "planes": WSP_KERNELS_PLANES}
 
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
             "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
@@ -60,6 +63,9 @@ class wsp_params(ctypes.Structure):
         ("kmeans_tol", ctypes.c_double),
         ("kmeans_max_iter", ctypes.c_int32),
         ("device", ctypes.c_int32),
+        ("kernel_mode", ctypes.c_int32),
+        ("plane_dq", ctypes.c_double),
+        ("plane_dw", ctypes.c_double),
     ]
 
 
@@ -239,7 +245,11 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
                 kb_beta: float = 0.0, support_scale: float = 1.0, n_stacks: int = 1,
                 fold: bool = False, quad_tol: float = 1e-6, quad_max_panels: int = 1024,
                 max_support: int = 1024, precision: str = "fp32_fp64phase",
-                kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, device: int = 0) -> wsp_params:
+                kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, device: int = 0,
+                kernels: str = "exact", plane_dq: float = 0.0, plane_dw: float = 0.0) -> wsp_params:
+    """Parameters with the library defaults; ``kernels="planes"`` selects taps
+    interpolated on the fly from pre-sampled 1-D w-planes (steps plane_dq in
+    cells, plane_dw in wavelengths; 0 = the library's defaults 1/64, 1/16)."""
     p = wsp_default_params()
     p.n = n
     p.fov_rad = fov_rad
@@ -257,6 +267,9 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
     p.kmeans_tol = kmeans_tol
     p.kmeans_max_iter = kmeans_max_iter
     p.device = device
+    p.kernel_mode = KERNEL_MODES[kernels]
+    p.plane_dq = plane_dq
+    p.plane_dw = plane_dw
     return p
 
 

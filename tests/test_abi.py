@@ -36,7 +36,8 @@ def test_default_params():
     ("n", 63), ("n", 0), ("oversample", 0.5), ("fov_rad", 0.0), ("fov_rad", 0.6),
     ("kb_support", 3), ("support_scale", 0.5), ("n_stacks", 0), ("fold_conjugate", 2),
     ("quad_max_panels", 4), ("quad_max_panels", 5000), ("precision", 7), ("kmeans_max_iter", 0),
-    ("max_support", 2),
+    ("max_support", 2), ("kernel_mode", 7), ("plane_dq", -1.0), ("plane_dq", 2.0),
+    ("plane_dw", float("nan")),
 ])
 def test_create_rejects_invalid_parameters(field, value):
     p = wsp.make_params(64, math.radians(10.0))
@@ -45,6 +46,35 @@ def test_create_rejects_invalid_parameters(field, value):
         wsp.wsp_create(p)
     assert ei.value.status == wsp.WSP_EINVAL
     assert wsp.wsp_last_error()
+
+
+def test_plane_mode_needs_fp32_path():
+    p = wsp.make_params(64, math.radians(10.0), precision="fp64", kernels="planes")
+    with pytest.raises(wsp.WspError) as ei:
+        wsp.wsp_create(p)
+    assert ei.value.status == wsp.WSP_EINVAL
+
+
+def test_params_layout_matches_header(tmp_path):
+    """ctypes mirror of wsp_params has the C struct's size and field offsets."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in wsp.wsp_params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"wsp.h\"\nint main(void){\n"
+                   "printf(\"%zu\\n\", sizeof(wsp_params));\n" +
+                   "".join(f"printf(\"%zu\\n\", offsetof(wsp_params, {f}));\n" for f in fields) +
+                   "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(wsp.wsp_params)
+    assert out[1:] == [getattr(wsp.wsp_params, f).offset for f in fields]
 
 
 def test_grid_side_must_tile():

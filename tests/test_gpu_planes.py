@@ -1,0 +1,195 @@
+"""GPU parity of the w-plane kernel mode (Sec. 5.1.1) against the oracle.
+
+In this mode the GPU integrates Eq. (6) on the lattice K(i dq, j dw), q, w >= 0
+(quadrature tolerance 1e-6 of the plane's peak, values stored as complex64),
+and interpolates every tap bilinearly in FP32 inside degrid and grid; the
+oracle interpolates its FP64 lattice with the same steps (oracle/presample.py).
+
+Per tap the two differ by the lattice values (quadrature tolerance and FP32
+storage, a few 1e-6 of the peak) and by the FP32 tap distance: q comes from
+FP32 offsets of at most J_p cells, with a relative error of a few 2^-24, and
+an error dq in q moves the interpolant by at most its slope times dq, the
+slope being bounded by max |dK/dq| <= 2 pi r_max max|K| (r_max = alpha / 2
+= 1).  Hence the per-tap bound used below:
+    |K_gpu - K_oracle| <= peak (5e-6 + 2 pi * 8 * 2^-24 * q) ~ peak (5e-6 + 3e-6 q).
+Operator outputs are sums of such taps; their tolerance, 5e-5 relative, is
+stated from the bound at the sampled supports' typical q.
+
+Workloads: a 64^2, 25 deg problem with folded visibilities in two w-stacks
+(every tap and the whole operator), and two full-size workloads in the
+benchmark's launch configuration, checked on stratified samples: the 1024^2
+single-stack workload (1e6 visibilities, supports up to 282, the large-entry
+kernels) and the 2048^2 8-stack workload (5e6 visibilities, the small-entry
+kernels).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operator, presample, stacking, wkernel
+from paper_1903_06555_amd import synthetic as syn
+from paper_1903_06555_amd import wsp
+
+pytestmark = pytest.mark.gpu
+
+TWO_PI_8_ULP = 2.0 * math.pi * 8.0 * 2.0 ** -24
+
+
+def tap_tolerance(u_pix, v_pix, jp, peak):
+    _, _, q = wkernel.tap_geometry(u_pix, v_pix, jp)
+    return peak * (5e-6 + TWO_PI_8_ULP * q)
+
+
+def check_taps(op, ref, p):
+    K, u0, v0 = op.kernel(int(p))
+    ru0, rv0, Kr = ref.kernel(int(p))
+    assert (u0, v0) == (ru0, rv0)
+    peak = float(np.max(np.abs(Kr)))
+    tol = tap_tolerance(ref.u_pix[p], ref.v_pix[p], Kr.shape[0], peak)
+    excess = float(np.max(np.abs(K - Kr) / tol))
+    assert excess <= 1.0, (p, excess)
+    return float(np.max(np.abs(K - Kr))) / peak
+
+
+@pytest.fixture(scope="module")
+def small():
+    n, fov = 64, math.radians(25.0)
+    geom = wkernel.Geometry(n=n, fov=fov)
+    uvw = syn.uniform_box_uvw(2000, u_max=60.0, w_max=30.0, seed=41)
+    ps = presample.PlaneSampler(geom)
+    exact = operator.StackedOperator(geom, uvw, n_stacks=2, fold=True)
+    ref = operator.StackedOperator(geom, uvw, labels=exact.labels, centres=exact.centres, fold=True,
+                                   kernel_fn=ps.visibility_kernel)
+    params = wsp.make_params(n, fov, n_stacks=2, fold=True, kernels="planes")
+    op = wsp.Operator(params, uvw, labels=exact.labels, centres=exact.centres)
+    yield geom, uvw, exact, ref, op
+    op.close()
+
+
+def test_small_every_tap(small):
+    geom, uvw, exact, ref, op = small
+    assert op.build_status == 0
+    worst = max(check_taps(op, ref, p) for p in range(ref.m))
+    print(f"64^2 w-plane taps: max |dK| / peak = {worst:.2e}", flush=True)
+
+
+def test_small_operator(small):
+    geom, uvw, exact, ref, op = small
+    x = syn.point_source_sky(64, 10, "exp", seed=42, margin=4)
+    op.scratch.fill_(255)
+    y = op.degrid(torch.from_numpy(x)).cpu().numpy()
+    y_ref = ref.forward(x)
+    err_y = float(np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref))
+    yin = syn.random_vis(ref.m, seed=43)
+    op.scratch.fill_(255)
+    xa = op.grid(torch.from_numpy(yin)).cpu().numpy()
+    xr = ref.adjoint(yin)
+    err_x = float(np.linalg.norm(xa - xr) / np.linalg.norm(xr))
+    print(f"64^2 w-plane operator: degrid {err_y:.2e}, grid {err_x:.2e}", flush=True)
+    assert err_y <= 5e-5 and err_x <= 5e-5
+    # the interpolated operator stays within the interpolation level of the exact one
+    y_ex = exact.forward(x)
+    assert np.linalg.norm(y - y_ex) / np.linalg.norm(y_ex) <= 2e-4
+
+
+def test_small_planes_smaller_than_taps(small):
+    geom, uvw, exact, ref, op = small
+    assert op.footprint["kernel_bytes"] > 0
+    # pair rows of 16-byte samples, against 8 bytes per tap of the exact mode
+    assert op.footprint["kernel_bytes"] % 16 == 0
+
+
+def test_small_build_parts(small):
+    # a part-wise build gives the same operator
+    geom, uvw, exact, ref, op = small
+    params = wsp.make_params(64, geom.fov, n_stacks=2, fold=True, kernels="planes")
+    op2 = wsp.Operator(params, uvw, labels=exact.labels, centres=exact.centres, build=False)
+    try:
+        seen = []
+        op2.build(part=700, progress=lambda d, n: seen.append(d))
+        assert seen == [700, 1400, 2000]
+        x = torch.from_numpy(syn.point_source_sky(64, 10, "exp", seed=42, margin=4))
+        assert torch.equal(op2.degrid(x), op.degrid(x))
+    finally:
+        op2.close()
+
+
+FULL = {  # workload: (k-means iterations of the oracle's assignment, stacks sampled)
+    "mwa_1024_single_stack": (100, 1),
+    "mwa_2048_8_stacks": (100, 4),
+}
+
+
+@pytest.fixture(scope="module", params=list(FULL))
+def full(request):
+    name = request.param
+    iters, n_sample_stacks = FULL[name]
+    wl = syn.WORKLOADS[name]
+    uvw = syn.workload_uvw(wl)
+    geom = wkernel.Geometry(n=wl.n, fov=math.radians(wl.fov_deg))
+    folded = stacking.fold(uvw)[0] if wl.fold else uvw
+    labels, centres, _ = stacking.kmeans_w(folded[:, 2], wl.n_stacks, 1e-3, iters)
+    ps = presample.PlaneSampler(geom)
+    ref = operator.StackedOperator(geom, uvw, n_stacks=wl.n_stacks, fold=wl.fold, labels=labels,
+                                   centres=centres, kernel_fn=ps.visibility_kernel)
+    params = wsp.make_params(wl.n, geom.fov, n_stacks=wl.n_stacks, fold=wl.fold,
+                             precision=wl.precision, kernels="planes")
+    op = wsp.Operator(params, uvw, labels=ref.labels, centres=ref.centres)
+    stacks = np.unique(np.linspace(0, wl.n_stacks - 1, n_sample_stacks).astype(int))
+    sample = []
+    for k in stacks:
+        members = np.flatnonzero(ref.labels == k)
+        order = members[np.argsort(ref.jp[members], kind="stable")]
+        pick = (np.array([0.05, 0.5, 0.95, 1.0]) * (order.size - 1)).astype(int)
+        sample.extend(order[pick].tolist())
+    sample = np.unique(np.array(sample))
+    print(f"{name}: w-plane lattice {op.footprint['kernel_bytes'] / 2**20:.1f} MiB, "
+          f"sample J_p {ref.jp[sample].tolist()}", flush=True)
+    yield name, wl, ref, op, sample
+    op.close()
+
+
+def test_full_sampled_taps(full):
+    name, wl, ref, op, sample = full
+    worst = max(check_taps(op, ref, p) for p in sample)
+    print(f"{name}: sampled w-plane taps max |dK| / peak = {worst:.2e}", flush=True)
+
+
+def test_full_sampled_degrid(full):
+    name, wl, ref, op, sample = full
+    x = syn.workload_sky(wl)
+    op.scratch.fill_(255)
+    y = op.degrid(torch.from_numpy(x)).cpu().numpy()
+    assert np.isfinite(y).all()
+    y_ref = ref.forward(x, subset=sample)[sample]
+    err = float(np.linalg.norm(y[sample] - y_ref) / np.linalg.norm(y_ref))
+    print(f"{name}: sampled w-plane degrid rel err {err:.2e}", flush=True)
+    assert err <= 5e-5
+
+
+def test_full_sampled_grid(full):
+    name, wl, ref, op, sample = full
+    yin = np.zeros(ref.m, dtype=np.complex128)
+    yin[sample] = syn.random_vis(sample.size, seed=44)
+    op.scratch.fill_(255)
+    xa = op.grid(torch.from_numpy(yin)).cpu().numpy()
+    assert np.isfinite(xa).all()
+    xr = ref.adjoint(yin, subset=sample)
+    err = float(np.linalg.norm(xa - xr) / np.linalg.norm(xr))
+    print(f"{name}: sampled w-plane grid rel err {err:.2e}", flush=True)
+    assert err <= 5e-5
+
+
+def test_full_adjoint_identity(full):
+    name, wl, ref, op, sample = full
+    xr = torch.from_numpy(syn.random_image(wl.n, seed=45))
+    yr = torch.from_numpy(syn.random_vis(ref.m, seed=46))
+    Phx = op.degrid(xr).cpu().numpy().astype(np.complex128)
+    Phty = op.grid(yr).cpu().numpy().astype(np.float64)
+    lhs = float(np.real(np.vdot(Phx, yr.numpy())))
+    rhs = float(np.sum(xr.numpy() * Phty))
+    rel = abs(lhs - rhs) / abs(lhs)
+    print(f"{name}: w-plane adjoint identity {rel:.2e}", flush=True)
+    assert rel <= 1e-4
