@@ -202,6 +202,24 @@ wsp_status wsp_degrid(wsp_ctx *ctx, const void *image, void *vis, void *stream);
  * overwritten.  Asynchronous on the stream.  Errors as wsp_degrid. */
 wsp_status wsp_grid(wsp_ctx *ctx, const void *vis, void *image, void *stream);
 
+/* Linear polarisation (Sec. 3.3, Eq. (9)).  Stokes Q and U are real images,
+ * P = Q + iU and y_P = y_Q + i y_U.  Folding reflects each real Stokes image's
+ * visibilities on its own: for a folded visibility (w < 0 given)
+ *     y_P(u, v, w) = conj( y_Q(-u, -v, -w) - i y_U(-u, -v, -w) ),
+ * not the conjugate of y_P itself.  wsp_degrid_pol: vis = Phi Q + i Phi U,
+ * each Phi with its Eq. (8) conjugation.  q_image, u_image: device real [N][N];
+ * vis: device complex [M] (caller order), overwritten.  Runs the degrid
+ * pipeline twice; vis must not alias an image.  Asynchronous on the stream.
+ * Errors as wsp_degrid. */
+wsp_status wsp_degrid_pol(wsp_ctx *ctx, const void *q_image, const void *u_image, void *vis,
+                          void *stream);
+
+/* Adjoint of wsp_degrid_pol under the real inner product:
+ *     q_image = Re Phi^dagger vis,   u_image = Re Phi^dagger (-i vis),
+ * each overwritten (device real [N][N], distinct).  Asynchronous on the
+ * stream.  Errors as wsp_grid, WSP_EINVAL if the two images are the same buffer. */
+wsp_status wsp_grid_pol(wsp_ctx *ctx, const void *vis, void *q_image, void *u_image, void *stream);
+
 /* Test hook: copy the taps of visibility p (caller order) to host memory
  * (complex, J_p^2 values, row-major [row][col], rows along v) and return J_p
  * and the unwrapped base indices U0, V0.  out may be NULL to query J_p only.

@@ -578,6 +578,28 @@ wsp_status wsp_grid(wsp_ctx *c, const void *vis, void *image, void *stream) {
     return WSP_OK;
 }
 
+wsp_status wsp_degrid_pol(wsp_ctx *c, const void *q_image, const void *u_image, void *vis,
+                          void *stream) {
+    if (!c || !q_image || !u_image || !vis) return fail(WSP_EINVAL, "null argument");
+    if (!c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(run_degrid(c, q_image, vis, s, 0), "degrid (Stokes Q)");
+    HIP_OR_FAIL(run_degrid(c, u_image, vis, s, 1), "degrid (Stokes U)");
+    return WSP_OK;
+}
+
+wsp_status wsp_grid_pol(wsp_ctx *c, const void *vis, void *q_image, void *u_image, void *stream) {
+    if (!c || !q_image || !u_image || !vis) return fail(WSP_EINVAL, "null argument");
+    if (q_image == u_image) return fail(WSP_EINVAL, "q_image and u_image must differ");
+    if (!c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(run_grid(c, vis, q_image, s, 0), "grid (Stokes Q)");
+    HIP_OR_FAIL(run_grid(c, vis, u_image, s, 1), "grid (Stokes U)");
+    return WSP_OK;
+}
+
 wsp_status wsp_kernel_values(wsp_ctx *c, int64_t p, void *out, int32_t *jp, int32_t *u0,
                              int32_t *v0) {
     if (!c) return fail(WSP_EINVAL, "null argument");

@@ -245,15 +245,21 @@ __device__ __forceinline__ R wave_sum_r(R x) {
 }
 
 // W_k and Eq. (8) on the adjoint's input: yw[p] = W_p (conj) y[perm[p]] in
-// sorted order.
+// sorted order.  rot = 1 takes -i y instead (the Stokes U half of the
+// polarised adjoint, Eq. (9)).
 template <bool kFP64>
 __global__ void k_prep_vis(const typename Types<kFP64>::C *__restrict__ vis,
-                           typename Types<kFP64>::C *yw, ApplyArgs a) {
+                           typename Types<kFP64>::C *yw, ApplyArgs a, int rot) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.m) return;
     C y = vis[a.perm[p]];
+    if (rot) {
+        const R re = y.x;
+        y.x = y.y;
+        y.y = -re;
+    }
     R w = (R)a.wt[p];
     C o;
     o.x = y.x * w;
@@ -588,10 +594,12 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
 }
 
 // y[perm[p]] = W_p (conj) sum of visibility p's entry partials, in entry order.
+// add_i = 1 adds i times that value to y[perm[p]] instead (the Stokes U half
+// of the polarised degrid: each Stokes image is folded on its own, Eq. (9)).
 template <bool kFP64>
 __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpart,
                                 const int64_t *__restrict__ ent_off,
-                                typename Types<kFP64>::C *vis, ApplyArgs a) {
+                                typename Types<kFP64>::C *vis, ApplyArgs a, int add_i) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -606,6 +614,12 @@ __global__ void k_degrid_reduce(const typename Types<kFP64>::C *__restrict__ dpa
     C y;
     y.x = ar * w;
     y.y = (a.sflag[p] ? -ai : ai) * w;  // Eq. (8): folded visibilities are conjugated
+    if (add_i) {
+        C o = vis[a.perm[p]];
+        o.x -= y.y;
+        o.y += y.x;
+        y = o;
+    }
     vis[a.perm[p]] = y;
 }
 
@@ -1048,7 +1062,7 @@ __global__ void k_plane_vis_taps(const double *__restrict__ ux, const double *__
 
 template <bool kFP64>
 hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_centres,
-                    hipStream_t s) {
+                    hipStream_t s, int add_i) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     const Geom &g = c->g;
@@ -1088,14 +1102,14 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
         }
     }
     hipLaunchKernelGGL(k_degrid_reduce<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s,
-                       (const C *)c->scratch_dpart, pl.ent_off, (C *)vis, a);
+                       (const C *)c->scratch_dpart, pl.ent_off, (C *)vis, a, add_i);
     stage_end(c, kStDegrid, ev, s);
     return hipGetLastError();
 }
 
 template <bool kFP64>
 hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_centres,
-                  hipStream_t s) {
+                  hipStream_t s, int rot) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     const Geom &g = c->g;
@@ -1109,7 +1123,7 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
                 pl.item_slot, c->scratch_part, pl.n_items,    pl.tile_bits, g.G};
     ev = stage_begin(c, s);
     hipLaunchKernelGGL(k_prep_vis<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)vis,
-                       (C *)c->scratch_yw, a);
+                       (C *)c->scratch_yw, a, rot);
     set_plane_args(c, &ta);
     if (pl.n_items > 0) {
         unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
@@ -1151,14 +1165,14 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
 
 }  // namespace
 
-hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s) {
-    if (c->p.precision == WSP_FP64) return degrid_t<true>(c, image, vis, c->plan_centres, s);
-    return degrid_t<false>(c, image, vis, c->plan_centres, s);
+hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s, int add_i) {
+    if (c->p.precision == WSP_FP64) return degrid_t<true>(c, image, vis, c->plan_centres, s, add_i);
+    return degrid_t<false>(c, image, vis, c->plan_centres, s, add_i);
 }
 
-hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s) {
-    if (c->p.precision == WSP_FP64) return grid_t<true>(c, vis, image, c->plan_centres, s);
-    return grid_t<false>(c, vis, image, c->plan_centres, s);
+hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s, int rot) {
+    if (c->p.precision == WSP_FP64) return grid_t<true>(c, vis, image, c->plan_centres, s, rot);
+    return grid_t<false>(c, vis, image, c->plan_centres, s, rot);
 }
 
 hipError_t run_plane_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s) {

@@ -204,8 +204,10 @@ hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);
 void stage_end(wsp_ctx *c, int stage, hipEvent_t start, hipStream_t s);
 
 // apply.hip
-hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s);
-hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s);
+// add_i = 1: vis += i Phi image (instead of vis = Phi image); rot = 1: image =
+// Re Phi^dagger (-i vis).  These are the Stokes U halves of Eq. (9).
+hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s, int add_i = 0);
+hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s, int rot = 0);
 hipError_t run_plane_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s);
 
 }  // namespace wsp

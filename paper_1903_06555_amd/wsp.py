@@ -39,7 +39,7 @@ KERNEL_MODES = {"exact": WSP_KERNELS_EXACT, "planes": WSP_KERNELS_PLANES}
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
             "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
             "wsp_build_kernels", "wsp_build_kernels_part", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
-            "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
+            "wsp_degrid_pol", "wsp_grid_pol", "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
             "wsp_last_error")
 
 STAGES = ("taper_pad", "fft_forward", "degrid", "zero", "grid", "fft_inverse", "crop_untaper")
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
         "wsp_quad_stats": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "wsp_degrid": (i32, [P, P, P, P]),
         "wsp_grid": (i32, [P, P, P, P]),
+        "wsp_degrid_pol": (i32, [P, P, P, P, P]),
+        "wsp_grid_pol": (i32, [P, P, P, P, P]),
         "wsp_kernel_values": (i32, [P, i64, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]),
         "wsp_set_timing": (i32, [P, i32]),
@@ -207,6 +209,14 @@ def wsp_degrid(ctx, image: torch.Tensor, vis: torch.Tensor, stream=None):
 
 def wsp_grid(ctx, vis: torch.Tensor, image: torch.Tensor, stream=None):
     _check(load_library().wsp_grid(ctx, _ptr(vis), _ptr(image), _stream(stream)))
+
+
+def wsp_degrid_pol(ctx, q_image: torch.Tensor, u_image: torch.Tensor, vis: torch.Tensor, stream=None):
+    _check(load_library().wsp_degrid_pol(ctx, _ptr(q_image), _ptr(u_image), _ptr(vis), _stream(stream)))
+
+
+def wsp_grid_pol(ctx, vis: torch.Tensor, q_image: torch.Tensor, u_image: torch.Tensor, stream=None):
+    _check(load_library().wsp_grid_pol(ctx, _ptr(vis), _ptr(q_image), _ptr(u_image), _stream(stream)))
 
 
 def wsp_kernel_values(ctx, p: int, complex_dtype=np.complex64):
@@ -362,6 +372,28 @@ class Operator:
             out = torch.empty((self.n, self.n), dtype=self.real_dtype, device=self.device)
         wsp_grid(self.ctx, vis, out, stream)
         return out
+
+    def degrid_pol(self, q_image: torch.Tensor, u_image: torch.Tensor, out: torch.Tensor | None = None,
+                   stream=None):
+        """Linear-polarisation visibilities y_Q + i y_U, each Stokes image folded on its own (Eq. (9))."""
+        q_image = q_image.to(self.device, self.real_dtype).contiguous()
+        u_image = u_image.to(self.device, self.real_dtype).contiguous()
+        if q_image.shape != (self.n, self.n) or u_image.shape != (self.n, self.n):
+            raise ValueError(f"images must be {self.n}x{self.n}")
+        if out is None:
+            out = torch.empty(self.m, dtype=self.complex_dtype, device=self.device)
+        wsp_degrid_pol(self.ctx, q_image, u_image, out, stream)
+        return out
+
+    def grid_pol(self, vis: torch.Tensor, stream=None):
+        """(Re Phi^dagger vis, Re Phi^dagger (-i vis)): the adjoint of degrid_pol."""
+        vis = vis.to(self.device, self.complex_dtype).contiguous()
+        if vis.shape != (self.m,):
+            raise ValueError(f"vis must have {self.m} entries")
+        q = torch.empty((self.n, self.n), dtype=self.real_dtype, device=self.device)
+        u = torch.empty((self.n, self.n), dtype=self.real_dtype, device=self.device)
+        wsp_grid_pol(self.ctx, vis, q, u, stream)
+        return q, u
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
