@@ -59,10 +59,13 @@ class StackedOperator:
 
     def __init__(self, geom: Geometry, uvw, weights=None, n_stacks: int = 1,
                  fold: bool = False, labels=None, centres=None,
-                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, kernel_fn=None):
+                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, kernel_fn=None,
+                 extra_support: int = 0):
         self.geom = geom
         # (u_pix, v_pix, w_eff, geom, jp) -> (U0, V0, K): exact Eq. (6) taps by
-        # default, or e.g. presample.PlaneSampler(...).visibility_kernel
+        # default, or e.g. presample.PlaneSampler(...).visibility_kernel; a
+        # function with ``wants_index`` set also gets the visibility's index
+        # (keyword p).  extra_support widens every J_p (a DDE convolution).
         self.kernel_fn = wkernel.visibility_kernel if kernel_fn is None else kernel_fn
         uvw = np.asarray(uvw, dtype=np.float64)
         self.m = uvw.shape[0]
@@ -84,14 +87,15 @@ class StackedOperator:
         self.u_pix = uvw_f[:, 0] * geom.inv_du
         self.v_pix = uvw_f[:, 1] * geom.inv_du
         self.w_eff = uvw_f[:, 2] - self.centres[self.labels]
-        self.jp = wkernel.support(self.w_eff, geom)
+        self.jp = wkernel.support(self.w_eff, geom) + int(extra_support)
         self._kernels: dict[int, tuple] = {}
 
     def kernel(self, p: int):
         """(U0, V0, K[J_p, J_p]) of visibility p (cached)."""
         if p not in self._kernels:
+            extra = {"p": p} if getattr(self.kernel_fn, "wants_index", False) else {}
             self._kernels[p] = self.kernel_fn(
-                self.u_pix[p], self.v_pix[p], self.w_eff[p], self.geom, int(self.jp[p]))
+                self.u_pix[p], self.v_pix[p], self.w_eff[p], self.geom, int(self.jp[p]), **extra)
         return self._kernels[p]
 
     def _stack_members(self, subset):
