@@ -82,7 +82,21 @@ typedef struct wsp_params {
     int32_t kernel_mode;    /* WSP_KERNELS_EXACT or WSP_KERNELS_PLANES (see below)      */
     double plane_dq;        /* w-plane mode: sample step in q (cells); 0 selects 1/64   */
     double plane_dw;        /* w-plane mode: plane step in |w| (wavelengths); 0: 1/16   */
+    int32_t dde_support;    /* J_D: odd width of a per-visibility DDE kernel, 0 or 1 = none */
 } wsp_params;
+
+/* Direction-dependent effects (Sec. 5.2, Eq. (11)).  With dde_support = J_D
+ * >= 3 (odd, <= 15) every visibility's kernel becomes D_p * K_p, the discrete
+ * convolution of its w-projection kernel with a separable J_D x J_D kernel
+ * D_p[b, a] = d_v[p][b] d_u[p][a] given on the uv grid (a along u, b along v,
+ * offsets -h .. h, h = (J_D - 1) / 2):
+ *     K'_p[r, c] = sum_{a, b} d_v[p][b] d_u[p][a] K_p[r - b, c - a].
+ * Supports grow to J_p' = J + 2 ceil(|w - wbar| s f) + J_D - 1 (the base rule
+ * U0 = floor(u/du) - J_p'/2 + 1 is unchanged, so D is centred), and the taps
+ * hold K'.  The d arrays are set with wsp_set_dde before wsp_build_kernels;
+ * the convolution is applied in two 1-D passes (O(J_p'^2 J_D) per
+ * visibility).  Exact kernel mode only; J_D * max J_p' complex values must
+ * fit 64 KiB (WSP_ESUPPORT otherwise). */
 
 /* Kernel modes.
  *
@@ -136,6 +150,13 @@ wsp_status wsp_set_uvw(wsp_ctx *ctx, const double *uvw, int64_t m,
  * previous binding is dropped.  Errors: WSP_ESTATE, WSP_EINVAL, WSP_ESUPPORT. */
 wsp_status wsp_set_stacks(wsp_ctx *ctx, const int32_t *labels, const double *centres,
                           void *stream);
+
+/* DDE kernels (dde_support = J_D >= 3): d_u, d_v are device complex [M][J_D]
+ * (complex64 or complex128 by precision) in the caller's order; both are
+ * copied.  Required before wsp_build_kernels when J_D >= 3; kept across
+ * wsp_set_stacks, dropped by wsp_set_uvw.  Errors: WSP_ESTATE (no
+ * visibilities yet, or dde_support < 3), WSP_EINVAL, WSP_EHIP. */
+wsp_status wsp_set_dde(wsp_ctx *ctx, const void *d_u, const void *d_v, void *stream);
 
 /* Copy out the stack assignment (host: labels [M] in caller order or NULL,
  * centres [K]) and the number of k-means iterations run (0 after

@@ -125,6 +125,11 @@ wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
         c->planned = false;
         return fail(WSP_EINVAL, "a visibility lies beyond 1e9 grid cells");
     }
+    if (c->g.dde_h > 0 &&
+        (size_t)(2 * c->g.dde_h + 1) * (size_t)c->plan.max_jp * cplx_bytes(c) > 65536) {
+        c->planned = false;
+        return fail(WSP_ESUPPORT, "DDE convolution: J_D x max J_p' complex values exceed 64 KiB");
+    }
     if (c->g.planes) {
         bool too_large = false;
         e = plane_setup(c, s, &too_large);
@@ -265,6 +270,10 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
         return fail(WSP_EINVAL, "unknown kernel_mode");
     if (p.kernel_mode == WSP_KERNELS_PLANES && p.precision != WSP_FP32_FP64PHASE)
         return fail(WSP_EINVAL, "w-plane kernels need precision WSP_FP32_FP64PHASE");
+    if (p.dde_support < 0 || p.dde_support > 15 || (p.dde_support > 1 && p.dde_support % 2 == 0))
+        return fail(WSP_EINVAL, "dde_support must be 0, 1 or odd in [3, 15]");
+    if (p.dde_support > 1 && p.kernel_mode == WSP_KERNELS_PLANES)
+        return fail(WSP_EINVAL, "DDE convolution needs stored (exact) kernels");
     if (!(p.plane_dq >= 0.0) || !(p.plane_dw >= 0.0) || !std::isfinite(p.plane_dq) ||
         !std::isfinite(p.plane_dw) || p.plane_dq > 1.0)
         return fail(WSP_EINVAL, "plane_dq must be in [0, 1] and plane_dw >= 0 (0 = default)");
@@ -293,6 +302,7 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     g.plane_dw = p.plane_dw > 0.0 ? p.plane_dw : 1.0 / 16.0;
     g.plane_inv_dq = 1.0 / g.plane_dq;
     g.plane_inv_dw = 1.0 / g.plane_dw;
+    g.dde_h = p.dde_support > 1 ? (p.dde_support - 1) / 2 : 0;
     double xr = 2.0 * M_PI * g.a * g.r_max;
     double ymax = std::fmax(0.25 * g.beta * g.beta, std::fabs(0.25 * (g.beta * g.beta - xr * xr)));
     int terms = (int)std::ceil(2.0 * std::sqrt(ymax)) + 30;
@@ -359,6 +369,10 @@ wsp_status wsp_set_uvw(wsp_ctx *c, const double *uvw, int64_t m, const double *w
     Plan &pl = c->plan;
     free_sorted_plan(pl);
     free_caller(pl);
+    hipFree(c->dde_u);
+    hipFree(c->dde_v);
+    c->dde_u = c->dde_v = nullptr;
+    c->dde_set = false;
     c->planned = c->bound = c->built = false;
     pl.m = m;
     HIP_OR_FAIL(hipMalloc(&pl.u, sizeof(double) * m), "hipMalloc");
@@ -430,6 +444,24 @@ wsp_status wsp_set_stacks(wsp_ctx *c, const int32_t *labels, const double *centr
     c->centres.assign(centres, centres + K);
     c->iterations = 0;
     return finish_plan(c, s);
+}
+
+wsp_status wsp_set_dde(wsp_ctx *c, const void *d_u, const void *d_v, void *stream) {
+    if (!c || !d_u || !d_v) return fail(WSP_EINVAL, "null argument");
+    if (!c->plan.u) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    if (c->g.dde_h == 0) return fail(WSP_ESTATE, "dde_support is not set (>= 3)");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    const size_t bytes = (size_t)c->plan.m * (size_t)(2 * c->g.dde_h + 1) * cplx_bytes(c);
+    if (!c->dde_u) HIP_OR_FAIL(hipMalloc(&c->dde_u, bytes), "hipMalloc");
+    if (!c->dde_v) HIP_OR_FAIL(hipMalloc(&c->dde_v, bytes), "hipMalloc");
+    hipStream_t s = as_stream(stream);
+    HIP_OR_FAIL(hipMemcpyAsync(c->dde_u, d_u, bytes, hipMemcpyDeviceToDevice, s), "DDE copy");
+    HIP_OR_FAIL(hipMemcpyAsync(c->dde_v, d_v, bytes, hipMemcpyDeviceToDevice, s), "DDE copy");
+    HIP_OR_FAIL(hipStreamSynchronize(s), "DDE copy");
+    c->dde_set = true;
+    c->built = false;
+    c->built_upto = 0;
+    return WSP_OK;
 }
 
 wsp_status wsp_get_stacks(const wsp_ctx *c, int32_t *labels, double *centres, int32_t *iterations) {
@@ -517,6 +549,7 @@ wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void
     if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
     if (!c->bound) return fail(WSP_ENOMEM_BINDING, "wsp_bind_memory first");
     if (first != c->built_upto) return fail(WSP_ESTATE, "parts must be built in order from 0");
+    if (c->g.dde_h > 0 && !c->dde_set) return fail(WSP_ESTATE, "wsp_set_dde first");
     if (count <= 0 || first + count > c->plan.m) return fail(WSP_EINVAL, "bad visibility range");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = as_stream(stream);
@@ -684,6 +717,8 @@ void wsp_destroy(wsp_ctx *c) {
     for (hipEvent_t ev : c->timer.pool) hipEventDestroy(ev);
     free_sorted_plan(c->plan);
     free_caller(c->plan);
+    hipFree(c->dde_u);
+    hipFree(c->dde_v);
     hipFree(c->plan_centres);
     if (c->fft_v_made) hipfftDestroy(c->fft_v);
     if (c->fft_u_made) hipfftDestroy(c->fft_u);

@@ -23,6 +23,8 @@
 // sums in FP32, accumulated over the partition in FP64.  FP64 path: all FP64.
 #include <hipcub/hipcub.hpp>
 
+#include <type_traits>
+
 #include "wsp_devmath.h"
 
 namespace wsp {
@@ -76,6 +78,10 @@ struct BuildArgs {
     int n_pairs;
     double plane_dq, plane_dw;
     float2 *table2;
+    // DDE convolution (g.dde_h > 0): per-visibility kernels, caller order, and
+    // the sorted -> caller permutation
+    const void *dde_u, *dde_v;
+    const int32_t *perm;
     const int32_t *border;
     int64_t m;
     const double *ux, *vx, *weff;
@@ -88,6 +94,12 @@ struct BuildArgs {
     int max_panels;
     unsigned long long *stats;
 };
+
+// Outer ring of width h of a J_p' x J_p' block: the DDE convolution's margin,
+// where the w-kernel itself is zero (Eq. (11)).
+__device__ __forceinline__ bool in_dde_ring(int row, int col, int jp, int h) {
+    return h > 0 && (row < h || row >= jp - h || col < h || col >= jp - h);
+}
 
 // Samples of plane j: as many as the pair row that reads the most of them
 // (row j, or row j - 1 for the last plane; rows grow with j).
@@ -494,10 +506,13 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         if (t < ntap) {
             const int row = (int)(t / jp), col = (int)(t - (int64_t)(t / jp) * jp);
             const int64_t pos = off + blocked_tap_index(row, col, jp, u0w, v0w);
+            // with a DDE convolution the w-kernel fills the inner block only
+            const bool ring = in_dde_ring(row, col, jp, g.dde_h);
             if constexpr (kFP64) {
-                ((double2 *)A.taps)[pos] = make_double2(accr[k], acci[k]);
+                ((double2 *)A.taps)[pos] = ring ? make_double2(0.0, 0.0) : make_double2(accr[k], acci[k]);
             } else {
-                ((float2 *)A.taps)[pos] = make_float2((float)accr[k], (float)acci[k]);
+                ((float2 *)A.taps)[pos] = ring ? make_float2(0.0f, 0.0f)
+                                               : make_float2((float)accr[k], (float)acci[k]);
             }
         }
     }
@@ -544,11 +559,72 @@ __global__ __launch_bounds__(256) void k_interp(BuildArgs A, int64_t batch0,
             im = fma(lk, v.y, im);
         }
         const int64_t pos = off + blocked_tap_index(row, col, jp, u0w, v0w);
+        if (in_dde_ring(row, col, jp, A.g.dde_h)) re = im = 0.0;
         if constexpr (kFP64) {
             ((double2 *)A.taps)[pos] = make_double2(re, im);
         } else {
             ((float2 *)A.taps)[pos] = make_float2((float)re, (float)im);
         }
+    }
+}
+
+// DDE convolution of the built taps of a batch (Eq. (11)), one wavefront per
+// visibility, in place: K'[r, c] = sum_b d_v[b] H[r - b, c] with
+// H[r, c] = sum_a d_u[a] K[r, c - a] (a, b in -h .. h, out-of-block terms 0).
+// Row r of K is overwritten at step r; H row r + h is formed at step r from
+// K row r + h (not yet overwritten) into a ring of 2h + 1 rows in LDS, which
+// then holds every H row that output row r needs.
+template <bool kFP64>
+__global__ __launch_bounds__(64) void k_dde_conv(BuildArgs A, int64_t batch0) {
+    using C = typename std::conditional<kFP64, double2, float2>::type;
+    extern __shared__ char dde_lds[];
+    C *ring = (C *)dde_lds;
+    const int h = A.g.dde_h, JD = 2 * h + 1;
+    const int p = A.border[batch0 + blockIdx.x];
+    const int J = A.jp[p];
+    const int64_t cp = A.perm[p];
+    const C *du = (const C *)A.dde_u + cp * JD;
+    const C *dv = (const C *)A.dde_v + cp * JD;
+    C *taps = (C *)A.taps + A.tap_off[p];
+    const int u0w = A.u0w[p], v0w = A.v0w[p];
+    const int lane = threadIdx.x;
+    for (int r = -h; r < J; ++r) {
+        const int hr = r + h;  // H row formed at this step
+        C *slot = ring + (int64_t)(hr % JD) * J;
+        for (int c = lane; c < J; c += 64) {
+            C acc;
+            acc.x = 0;
+            acc.y = 0;
+            if (hr < J) {
+                for (int a = -h; a <= h; ++a) {
+                    const int cc = c - a;
+                    if (cc < 0 || cc >= J) continue;
+                    const C k = taps[blocked_tap_index(hr, cc, J, u0w, v0w)];
+                    const C d = du[a + h];
+                    acc.x += d.x * k.x - d.y * k.y;
+                    acc.y += d.x * k.y + d.y * k.x;
+                }
+            }
+            slot[c] = acc;
+        }
+        __syncthreads();
+        if (r >= 0) {
+            for (int c = lane; c < J; c += 64) {
+                C acc;
+                acc.x = 0;
+                acc.y = 0;
+                for (int b = -h; b <= h; ++b) {
+                    const int rr = r - b;
+                    if (rr < 0 || rr >= J) continue;
+                    const C hv = ring[(int64_t)(rr % JD) * J + c];
+                    const C d = dv[b + h];
+                    acc.x += d.x * hv.x - d.y * hv.y;
+                    acc.y += d.x * hv.y + d.y * hv.x;
+                }
+                taps[blocked_tap_index(r, c, J, u0w, v0w)] = acc;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -658,6 +734,14 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
                                    (const double2 *)samples, soff);
         }
         WSP_BSTEP(hipGetLastError());
+        if (A.g.dde_h > 0 && !A.plane_off) {
+            const size_t lds = (size_t)(2 * A.g.dde_h + 1) * pl.max_jp * cplx_bytes(c);
+            if (c->p.precision == WSP_FP64)
+                hipLaunchKernelGGL(k_dde_conv<true>, dim3(nb), dim3(64), lds, s, A, b0);
+            else
+                hipLaunchKernelGGL(k_dde_conv<false>, dim3(nb), dim3(64), lds, s, A, b0);
+            WSP_BSTEP(hipGetLastError());
+        }
     }
     WSP_BSTEP(hipStreamSynchronize(s));
     cleanup();
@@ -689,6 +773,9 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s)
     A.v0w = pl.v0w;
     A.tap_off = pl.tap_off;
     A.taps = c->taps;
+    A.dde_u = c->dde_u;
+    A.dde_v = c->dde_v;
+    A.perm = pl.perm;
     return run_build(c, A, first, count, s);
 }
 

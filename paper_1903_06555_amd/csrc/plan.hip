@@ -172,7 +172,7 @@ __global__ void k_support(const double *__restrict__ u, const double *__restrict
         atomicOr(err, 1);
         half_extra = 0.0;
     }
-    int jp = g.J + 2 * (int)half_extra;
+    int jp = g.J + 2 * (int)half_extra + 2 * g.dde_h;  // + J_D - 1 with a DDE convolution
     if (jp > max_support) {
         atomicOr(err, 1);
         jp = g.J;

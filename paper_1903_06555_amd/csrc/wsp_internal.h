@@ -43,6 +43,8 @@ struct Geom {
     bool planes;
     double plane_dq, plane_inv_dq;
     double plane_dw, plane_inv_dw;
+    // DDE convolution (Eq. (11)): half width h of the per-visibility kernel D
+    int dde_h;
 };
 
 __host__ __device__ inline bool row_used(int V, const Geom &g) {
@@ -172,6 +174,9 @@ struct wsp_ctx {
     void *scratch_yw = nullptr;     // weighted adjoint input, sorted order (inside scratch)
     void *scratch_part = nullptr;   // partial tiles of shared grid tiles (inside scratch)
     void *scratch_dpart = nullptr;  // degrid partial sums, one per tile entry (inside scratch)
+    void *dde_u = nullptr;          // [M][J_D] DDE kernels along u and v, caller order (owned)
+    void *dde_v = nullptr;
+    bool dde_set = false;
     bool bound = false;
     bool built = false;
     int64_t built_upto = 0;         // visibilities built so far, in build order

@@ -37,7 +37,7 @@ WSP_KERNELS_PLANES = 1
 KERNEL_MODES = {"exact": WSP_KERNELS_EXACT, "planes": WSP_KERNELS_PLANES}
 
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
-            "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
+            "wsp_set_dde", "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
             "wsp_build_kernels", "wsp_build_kernels_part", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
             "wsp_degrid_pol", "wsp_grid_pol", "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
             "wsp_last_error")
@@ -66,6 +66,7 @@ class wsp_params(ctypes.Structure):
         ("kernel_mode", ctypes.c_int32),
         ("plane_dq", ctypes.c_double),
         ("plane_dw", ctypes.c_double),
+        ("dde_support", ctypes.c_int32),
     ]
 
 
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "wsp_create": (i32, [ctypes.POINTER(wsp_params), ctypes.POINTER(P)]),
         "wsp_set_uvw": (i32, [P, P, i64, P, P]),
         "wsp_set_stacks": (i32, [P, P, P, P]),
+        "wsp_set_dde": (i32, [P, P, P, P]),
         "wsp_get_stacks": (i32, [P, P, P, P]),
         "wsp_get_support": (i32, [P, P, P]),
         "wsp_footprint": (i32, [P, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
@@ -165,6 +167,10 @@ def wsp_set_uvw(ctx, uvw: torch.Tensor, weights: torch.Tensor | None = None, str
 
 def wsp_set_stacks(ctx, labels: np.ndarray, centres: np.ndarray, stream=None):
     _check(load_library().wsp_set_stacks(ctx, _ptr(labels), _ptr(centres), _stream(stream)))
+
+
+def wsp_set_dde(ctx, d_u: torch.Tensor, d_v: torch.Tensor, stream=None):
+    _check(load_library().wsp_set_dde(ctx, _ptr(d_u), _ptr(d_v), _stream(stream)))
 
 
 def wsp_get_stacks(ctx, labels: np.ndarray | None, centres: np.ndarray):
@@ -256,7 +262,8 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
                 fold: bool = False, quad_tol: float = 1e-6, quad_max_panels: int = 1024,
                 max_support: int = 1024, precision: str = "fp32_fp64phase",
                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, device: int = 0,
-                kernels: str = "exact", plane_dq: float = 0.0, plane_dw: float = 0.0) -> wsp_params:
+                kernels: str = "exact", plane_dq: float = 0.0, plane_dw: float = 0.0,
+                dde_support: int = 0) -> wsp_params:
     """Parameters with the library defaults; ``kernels="planes"`` selects taps
     interpolated on the fly from pre-sampled 1-D w-planes (steps plane_dq in
     cells, plane_dw in wavelengths; 0 = the library's defaults 1/64, 1/16)."""
@@ -280,6 +287,7 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
     p.kernel_mode = KERNEL_MODES[kernels]
     p.plane_dq = plane_dq
     p.plane_dw = plane_dw
+    p.dde_support = dde_support
     return p
 
 
@@ -320,6 +328,15 @@ class Operator:
         centres = np.ascontiguousarray(centres, dtype=np.float64)
         wsp_set_stacks(self.ctx, labels, centres, stream)
         self._bind()
+
+    def set_dde(self, d_u, d_v, stream=None):
+        """Per-visibility separable DDE kernels, complex [M, J_D] each (Eq. (11)); rebuild after."""
+        d_u = torch.as_tensor(np.asarray(d_u)).to(self.device, self.complex_dtype).contiguous()
+        d_v = torch.as_tensor(np.asarray(d_v)).to(self.device, self.complex_dtype).contiguous()
+        jd = self.params.dde_support
+        if d_u.shape != (self.m, jd) or d_v.shape != (self.m, jd):
+            raise ValueError(f"DDE kernels must be [{self.m}, {jd}]")
+        wsp_set_dde(self.ctx, d_u, d_v, stream)
 
     def build(self, stream=None, part: int | None = None, progress=None) -> int:
         """Build all kernels; with ``part``, in slices of that many visibilities,

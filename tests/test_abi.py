@@ -37,7 +37,7 @@ def test_default_params():
     ("kb_support", 3), ("support_scale", 0.5), ("n_stacks", 0), ("fold_conjugate", 2),
     ("quad_max_panels", 4), ("quad_max_panels", 5000), ("precision", 7), ("kmeans_max_iter", 0),
     ("max_support", 2), ("kernel_mode", 7), ("plane_dq", -1.0), ("plane_dq", 2.0),
-    ("plane_dw", float("nan")),
+    ("plane_dw", float("nan")), ("dde_support", 2), ("dde_support", 17), ("dde_support", -1),
 ])
 def test_create_rejects_invalid_parameters(field, value):
     p = wsp.make_params(64, math.radians(10.0))
@@ -50,6 +50,13 @@ def test_create_rejects_invalid_parameters(field, value):
 
 def test_plane_mode_needs_fp32_path():
     p = wsp.make_params(64, math.radians(10.0), precision="fp64", kernels="planes")
+    with pytest.raises(wsp.WspError) as ei:
+        wsp.wsp_create(p)
+    assert ei.value.status == wsp.WSP_EINVAL
+
+
+def test_dde_needs_stored_kernels():
+    p = wsp.make_params(64, math.radians(10.0), kernels="planes", dde_support=3)
     with pytest.raises(wsp.WspError) as ei:
         wsp.wsp_create(p)
     assert ei.value.status == wsp.WSP_EINVAL
