@@ -310,6 +310,21 @@ __global__ void k_entry_records(const int32_t *__restrict__ idx_sorted, const in
     wrec[s] = make_int4((int)(uint32_t)first, (int)(first >> 32), en.z, en.x);
 }
 
+// (stack, tile) key in the high 32 bits, the pair row floor(|w_eff| / dw) of
+// the entry's visibility in the low 32 (w-plane kernels).
+__global__ void k_entry_wkey(const uint32_t *__restrict__ keys, const int4 *__restrict__ ent,
+                             const double *__restrict__ weff, double inv_dw, int64_t E, uint64_t *k64) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const double a = fmin(floor(fabs(weff[ent[e].x]) * inv_dw), 4294967295.0);
+    k64[e] = ((uint64_t)keys[e] << 32) | (uint64_t)a;
+}
+
+__global__ void k_key_hi32(const uint64_t *__restrict__ k64, int64_t E, uint32_t *keys) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) keys[e] = (uint32_t)(k64[e] >> 32);
+}
+
 __global__ void k_entry_work(const uint32_t *__restrict__ keys_sorted,
                              const int32_t *__restrict__ idx_sorted, const int4 *__restrict__ ent,
                              int64_t E, int64_t *work, uint8_t *head) {
@@ -602,12 +617,42 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     while ((1 << stack_bits) < g.n_stacks) ++stack_bits;
     int key_bits = 2 * tile_bits + stack_bits;
     key_bits = key_bits > 0 ? key_bits : 1;
-    need = 0;
-    WSP_ESTEP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys_sorted, iota,
-                                                 pl.ent_sorted, (int)E, 0, key_bits, s));
-    WSP_ESTEP(scratch(need));
-    WSP_ESTEP(hipcub::DeviceRadixSort::SortPairs(tmp, need, keys, keys_sorted, iota, pl.ent_sorted,
-                                                 (int)E, 0, key_bits, s));
+    if (g.planes) {
+        // w-plane kernels: within a tile, entries in order of their visibility's
+        // lattice pair row, so the wavefronts working on neighbouring entries
+        // read the same lattice rows (cache reuse instead of one row each)
+        uint64_t *k64 = nullptr, *k64s = nullptr;
+        WSP_ESTEP(dalloc(&k64, E));
+        hipError_t e2 = dalloc(&k64s, E);
+        if (e2 == hipSuccess) {
+            hipLaunchKernelGGL(k_entry_wkey, dim3(grid1d(E, 256)), dim3(256), 0, s, keys, pl.ent, pl.weff,
+                               g.plane_inv_dw, E, k64);
+            e2 = hipGetLastError();
+        }
+        size_t need64 = 0;
+        if (e2 == hipSuccess)
+            e2 = hipcub::DeviceRadixSort::SortPairs(nullptr, need64, k64, k64s, iota, pl.ent_sorted, (int)E,
+                                                    0, 32 + key_bits, s);
+        if (e2 == hipSuccess) e2 = scratch(need64);
+        if (e2 == hipSuccess)
+            e2 = hipcub::DeviceRadixSort::SortPairs(tmp, need64, k64, k64s, iota, pl.ent_sorted, (int)E, 0,
+                                                    32 + key_bits, s);
+        if (e2 == hipSuccess) {
+            hipLaunchKernelGGL(k_key_hi32, dim3(grid1d(E, 256)), dim3(256), 0, s, k64s, E, keys_sorted);
+            e2 = hipGetLastError();
+        }
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);  // before k64 / k64s are released
+        hipFree(k64);
+        hipFree(k64s);
+        WSP_ESTEP(e2);
+    } else {
+        need = 0;
+        WSP_ESTEP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys_sorted, iota,
+                                                     pl.ent_sorted, (int)E, 0, key_bits, s));
+        WSP_ESTEP(scratch(need));
+        WSP_ESTEP(hipcub::DeviceRadixSort::SortPairs(tmp, need, keys, keys_sorted, iota, pl.ent_sorted,
+                                                     (int)E, 0, key_bits, s));
+    }
 
     // work items: cut each tile's entries every kItemTaps taps
     WSP_ESTEP(dalloc(&work, E));
