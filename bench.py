@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--m-vis", type=int, default=None, help="override visibility count (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--kernels", default="exact", choices=["exact", "planes"],
+                    help="exact per-visibility taps, or taps interpolated from 1-D w-planes")
     ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving", "build"],
                     help="operator: the metric; copy: a plain 2 GiB device copy used to "
                          "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE readings; serving: "
@@ -97,6 +99,15 @@ def algorithmic_bytes(stage: str, taps: int, m: int, cells: int, cb: int) -> int
     """
     per_vis = 8 + 4 + cb
     return taps * cb + m * per_vis + cells * cb
+
+
+# w-plane mode: FP32 operations per tap of the interpolation and the
+# multiply-add, counting an FMA as two (distance 6, lattice index 3, bilinear
+# complex interpolation 18, conjugation 1, complex multiply-add 8)
+PLANE_FLOPS_PER_TAP = 36
+# VALU FP32 peak without packed FP32 instructions (not used by this build):
+# 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
 def cpu_baseline(wl, uvw, x, y, sample_n: int):
@@ -364,8 +375,9 @@ def main():
     cdt = torch.complex128 if fp64 else torch.complex64
     cb = 16 if fp64 else 8
 
+    planes = args.kernels == "planes"
     params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
-                             precision=precision)
+                             precision=precision, kernels=args.kernels)
     t0 = time.perf_counter()
     op = wsp.Operator(params, uvw, build=False)
     torch.cuda.synchronize()
@@ -410,12 +422,27 @@ def main():
 
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     dom = "degrid" if per_launch["degrid"] >= per_launch["grid"] else "grid"
-    traffic = algorithmic_bytes(dom, taps, m, cells, cb)
-    achieved = traffic / (per_launch[dom] * 1e-3) / 1e9
+    if planes:
+        flops = PLANE_FLOPS_PER_TAP * taps
+        achieved_t = flops / (per_launch[dom] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved_t, "peak": VALU_FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved_t / VALU_FP32_PEAK_TFLOPS,
+                    "traffic": measured_traffic(dom, wl.name + "_planes", m, precision),
+                    "algorithmic_flops": flops, "flops_per_tap": PLANE_FLOPS_PER_TAP,
+                    "lattice_bytes": op.footprint["kernel_bytes"], "avg_launch_ms": per_launch[dom]}
+    else:
+        traffic = algorithmic_bytes(dom, taps, m, cells, cb)
+        achieved = traffic / (per_launch[dom] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(dom, wl.name, m, precision),
+                    "algorithmic_bytes": traffic, "avg_launch_ms": per_launch[dom]}
 
     y_host = y.cpu().numpy().astype(np.complex128)
     result = {
-        "metric": "Mvis/s degrid+grid with per-vis exact w-kernels; p50/p99 operator latency",
+        "metric": ("Mvis/s degrid+grid with w-kernels interpolated on the fly from 1-D w-planes; "
+                   "p50/p99 operator latency" if planes else
+                   "Mvis/s degrid+grid with per-vis exact w-kernels; p50/p99 operator latency"),
         "value": m / (ms_per_step * 1e-3) / 1e6,
         "unit": "Mvis/s",
         "n_gpus": 1,
@@ -429,12 +456,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "fov_deg": wl.fov_deg, "m_vis": m,
                    "n_stacks": wl.n_stacks, "fold": wl.fold, "precision": precision,
-                   "oversample": params.oversample, "kb_support": params.kb_support},
+                   "oversample": params.oversample, "kb_support": params.kb_support,
+                   **({"kernels": "planes", "plane_dq": 1 / 64, "plane_dw": 1 / 16} if planes else {})},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, wl.name, m, precision),
-                     "algorithmic_bytes": traffic, "avg_launch_ms": per_launch[dom]},
+        "roofline": roofline,
         "stages_ms_per_launch": per_launch,
         "setup": {"plan_s": t_plan, "build_s": t_build, "build_mvis_per_s": m / t_build / 1e6,
                   "kernel_bytes": op.footprint["kernel_bytes"], "taps": taps,
