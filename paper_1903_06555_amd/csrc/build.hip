@@ -206,9 +206,74 @@ __device__ float eval_panel_probes(double a, double b, double weff, double qstep
     return (float)err;
 }
 
+// The same G7/K15 estimates for the marked panels idx[0 .. ne), one
+// Gauss-Kronrod node per lane: 16-lane groups (15 nodes used) take 4 panels
+// per pass and sum their nodes with shuffles.  Used when a round has few
+// panels to evaluate, where one panel per lane would leave most lanes idle.
+// Panel idx[k]'s error goes to errv[idx[k]]; with acc the K15 values are
+// added into sre / sim of the group's first lane.
+__device__ void eval_marked_grouped(const float *cur, const int *idx, int ne, double weff, double qstep,
+                                    const Geom &g, float *errv, double *sre, double *sim, bool acc,
+                                    int lane) {
+    const int grp = lane >> 4, nd = lane & 15;
+    for (int k0 = 0; k0 < ne; k0 += kWave / 16) {
+        const int k = k0 + grp;
+        int pi = 0;
+        double a = 0.0, b = 0.0;
+        if (k < ne) {
+            pi = idx[k];
+            a = (double)fabsf(cur[pi]);
+            b = (double)fabsf(cur[pi + 1]);
+        }
+        const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+        double kr[kProbes], ki[kProbes], gr[kProbes], gi[kProbes];
+#pragma unroll
+        for (int j = 0; j < kProbes; ++j) kr[j] = ki[j] = gr[j] = gi[j] = 0.0;
+        if (k < ne && nd < WSP_GK_N) {
+            const double r = fma(half, wsp_gk_x[nd], mid);
+            double are, aim;
+            node_value(r, weff, g, &are, &aim);
+            const double wk = wsp_gk_wk[nd], wg = wsp_gk_wg[nd];
+#pragma unroll
+            for (int j = 0; j < kProbes; ++j) {
+                const double q = qstep * j;
+                const double x = kTwoPi * (r * q);
+                const double J = x < 8.0 ? j0_small(x) : j0_fp64(r, q, 8.0 / x, sqrt(0.6366197723675814 / x));
+                const double tr = are * J, ti = aim * J;
+                kr[j] = wk * tr;
+                ki[j] = wk * ti;
+                gr[j] = wg * tr;
+                gi[j] = wg * ti;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kProbes; ++j) {
+            for (int o = 8; o > 0; o >>= 1) {  // within the 16-lane group
+                kr[j] += __shfl_xor(kr[j], o, 64);
+                ki[j] += __shfl_xor(ki[j], o, 64);
+                gr[j] += __shfl_xor(gr[j], o, 64);
+                gi[j] += __shfl_xor(gi[j], o, 64);
+            }
+        }
+        if (k < ne && nd == 0) {
+            double err = 0.0;
+#pragma unroll
+            for (int j = 0; j < kProbes; ++j) {
+                const double dr = kr[j] - gr[j], di = ki[j] - gi[j];
+                err = fmax(err, half * sqrt(dr * dr + di * di));
+                if (acc) {
+                    sre[j] += half * kr[j];
+                    sim[j] += half * ki[j];
+                }
+            }
+            errv[pi] = (float)err;
+        }
+    }
+}
+
 // Phase 1.  Returns the panel count; the partition ends up in *out (LDS), as
 // |bnd[0]| < |bnd[1]| < ... < |bnd[P]|.
-__device__ int adaptive_partition(float *bA, float *bB, float **out, double weff, double qmax,
+__device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, double weff, double qmax,
                                   const BuildArgs &A, int lane, bool *capped) {
     const Geom &g = A.g;
     const double R = g.r_max;
@@ -248,15 +313,48 @@ __device__ int adaptive_partition(float *bA, float *bB, float **out, double weff
     constexpr int kChunks = kMaxPanels / kWave;
     for (int round = 0; round < 32; ++round) {
         float err[kChunks];
+        // panels to evaluate this round (marked by a negative boundary)
+        int ne = 0;
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            err[c] = -1.0f;
-            int i = c * kWave + lane;
-            if (c * kWave < P && i < P) {
-                float fa = cur[i];
-                if (signbit(fa)) {
-                    err[c] = eval_panel_probes((double)fabsf(fa), (double)fabsf(cur[i + 1]), weff,
-                                               qstep, g, sre, sim, round == 0);
+            if (c * kWave < P) {
+                const int i = c * kWave + lane;
+                ne += __popcll(__ballot(i < P && signbit(cur[i])));
+            }
+        }
+        if (ne <= kWave) {
+            // few panels: list them, evaluate one node per lane, errors via oth
+            int run = 0;
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                if (c * kWave < P) {
+                    const int i = c * kWave + lane;
+                    const bool mk = i < P && signbit(cur[i]);
+                    const unsigned long long bal = __ballot(mk);
+                    if (mk) idx[run + __popcll(bal & lanemask_lt(lane))] = i;
+                    run += __popcll(bal);
+                }
+            }
+            wave_sync();
+            eval_marked_grouped(cur, idx, ne, weff, qstep, g, oth, sre, sim, round == 0, lane);
+            wave_sync();
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int i = c * kWave + lane;
+                err[c] = (c * kWave < P && i < P && signbit(cur[i])) ? oth[i] : -1.0f;
+            }
+            wave_sync();  // oth is rewritten by the split below
+        } else {
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                err[c] = -1.0f;
+                int i = c * kWave + lane;
+                if (c * kWave < P && i < P) {
+                    float fa = cur[i];
+                    if (signbit(fa)) {
+                        err[c] = eval_panel_probes((double)fabsf(fa), (double)fabsf(cur[i + 1]), weff,
+                                                   qstep, g, sre, sim, round == 0);
+                    }
                 }
             }
         }
@@ -326,6 +424,7 @@ __device__ int adaptive_partition(float *bA, float *bB, float **out, double weff
 __global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, int nb,
                                                    float *part, int *npan) {
     __shared__ float s_bnd[kWavesPerBlock][2][kMaxPanels + 2];
+    __shared__ int s_idx[kWavesPerBlock][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int i = blockIdx.x * kWavesPerBlock + wid;
@@ -334,7 +433,7 @@ __global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, 
     const double weff = tg.weff, qmax = tg.ps.qmax;
     float *bnd = nullptr;
     bool capped = false;
-    int P = adaptive_partition(s_bnd[wid][0], s_bnd[wid][1], &bnd, weff, qmax, A, lane, &capped);
+    int P = adaptive_partition(s_bnd[wid][0], s_bnd[wid][1], s_idx[wid], &bnd, weff, qmax, A, lane, &capped);
     float *dst = part + (int64_t)i * (kMaxPanels + 2);
     for (int k = lane; k <= P; k += kWave) dst[k] = fabsf(bnd[k]);
     if (lane == 0) {
