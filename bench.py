@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--m-vis", type=int, default=None, help="override visibility count (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--stacks", type=int, default=None, help="override the workload's w-stack count")
+    ap.add_argument("--fold", type=int, choices=[0, 1], default=None,
+                    help="override the workload's conjugate-symmetry folding")
     ap.add_argument("--kernels", default="exact", choices=["exact", "planes"],
                     help="exact per-visibility taps, or taps interpolated from 1-D w-planes")
     ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving", "build"],
@@ -315,9 +318,33 @@ def build_rate(args):
     wl = syn.WORKLOADS[args.workload]
     m = args.m_vis or wl.m_vis
     precision = args.precision or wl.precision
+    n_stacks = args.stacks or wl.n_stacks
+    fold = wl.fold if args.fold is None else bool(args.fold)
     uvw = syn.workload_uvw(wl, m)
-    params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
+    params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=n_stacks, fold=fold,
                              precision=precision)
+    # a configuration whose exact taps exceed the device memory is reported by
+    # its footprint (e.g. one w-stack without folding on a wide field)
+    ctx = wsp.wsp_create(params)
+    try:
+        wsp.wsp_set_uvw(ctx, torch.as_tensor(uvw).cuda())
+        kb, gb, sb = wsp.wsp_footprint(ctx)
+        jp_all = np.empty(m, dtype=np.int32)
+        wsp.wsp_get_support(ctx, jp_all)
+    finally:
+        wsp.wsp_destroy(ctx)
+    free = torch.cuda.mem_get_info()[0]
+    if kb + gb + sb > 0.95 * free:
+        print(json.dumps({
+            "metric": "w-projection kernels built per second (adaptive quadrature, tol 1e-6)",
+            "mode": "build", "value": None, "unit": "vis/s", "fits": False,
+            "config": {"workload": wl.name, "n": wl.n, "m_vis": m, "n_stacks": n_stacks,
+                       "fold": fold, "precision": precision},
+            "kernel_bytes": kb, "grid_bytes": gb, "scratch_bytes": sb, "device_free_bytes": free,
+            "taps": int(np.sum(jp_all.astype(np.int64) ** 2)), "mean_jp": float(jp_all.mean()),
+            "max_jp": int(jp_all.max()),
+        }))
+        return
     t0 = time.perf_counter()
     op = wsp.Operator(params, uvw, build=False)
     torch.cuda.synchronize()
@@ -333,8 +360,8 @@ def build_rate(args):
     print(json.dumps({
         "metric": "w-projection kernels built per second (adaptive quadrature, tol 1e-6)",
         "mode": "build", "value": m / t_build, "unit": "vis/s", "dtype": "f32" if precision != "fp64" else "f64",
-        "config": {"workload": wl.name, "n": wl.n, "m_vis": m, "n_stacks": wl.n_stacks,
-                   "fold": wl.fold, "precision": precision},
+        "config": {"workload": wl.name, "n": wl.n, "m_vis": m, "n_stacks": n_stacks,
+                   "fold": fold, "precision": precision},
         "build_s": t_build, "plan_s": t_plan, "kmeans_iterations": iters,
         "taps": int(np.sum(jp.astype(np.int64) ** 2)), "mean_jp": float(jp.mean()),
         "max_jp": int(jp.max()), "quad_panels": panels, "quad_capped": capped,
