@@ -5,6 +5,16 @@ memory and streams.  Module-level functions mirror the C ABI in
 ``include/wsp.h`` one to one (``wsp_create``, ``wsp_set_uvw``, ...);
 :class:`Operator` strings them together for the common case.
 
+Beyond the Stokes operator (``Operator.degrid`` / ``Operator.grid``):
+
+- ``make_params(kernels="planes")`` interpolates every tap on the fly from
+  pre-sampled 1-D w-planes instead of storing per-visibility taps;
+- ``make_params(dde_support=J_D)`` with ``Operator.set_dde(d_u, d_v)``
+  convolves each kernel with a separable per-visibility DDE kernel;
+- ``Operator.degrid_pol`` / ``Operator.grid_pol`` apply the linear
+  polarisation operator y_P = Phi Q + i Phi U and its adjoint, each Stokes
+  image folded on its own.
+
 There is no fallback: if ``libwsp.so`` is missing or cannot be loaded the
 calls raise.
 """
