@@ -1,4 +1,4 @@
-"""Imaging loop (power method, FISTA) driven by the oracle operator on the CPU.
+"""Imaging loop (power method, FISTA, ADMM) driven by the oracle operator on the CPU.
 
 The solver is pinned by facts that do not depend on its code: the power
 method must return the largest eigenvalue of the dense matrix of
@@ -6,6 +6,12 @@ Re Phi^dagger Phi (built column by column, solved by numpy), and FISTA's
 result must satisfy the optimality (KKT) conditions of
 min 1/2 ||Phi x - y||^2 + lam ||x||_1, x >= 0:  with g = Re Phi^dagger (Phi x - y),
 g_i + lam = 0 where x_i > 0 and g_i + lam >= 0 where x_i = 0.
+
+ADMM for the constrained form of Eq. (10) (min ||x||_1 subject to
+||Phi x - y|| <= eps, x >= 0) is pinned by the equivalence of the two forms:
+with eps the residual of the penalised solution at lam, both have the same
+minimiser, so ADMM must land on FISTA's point, on the ball's boundary, where
+g is constant (= -c, c > 0) on the support and >= -c elsewhere.
 """
 import math
 
@@ -81,3 +87,23 @@ def test_fista_reaches_kkt_point(small):
     # the three sources are found at their pixels
     for (j, i) in [(5, 7), (10, 3), (8, 12)]:
         assert x[j, i] > 0.5 * sky[j, i]
+
+
+def test_admm_constrained_matches_penalised_solution(small):
+    op, sky, y = small
+    L = imaging.power_norm2(op, n_iter=300, tol=1e-13)
+    lam = 0.01 * float(torch.max(torch.abs(op.grid(y))))
+    fi = imaging.fista_l1(op, y, lam, n_iter=600, norm2=L, track=False)
+    eps = float(torch.linalg.vector_norm(op.degrid(fi.x) - y))
+    ad = imaging.admm_l1_ball(op, y, eps, mu=lam, n_iter=800, norm2=L)
+    x, xf = ad.x.numpy(), fi.x.numpy()
+    assert np.linalg.norm(x - xf) <= 1e-5 * np.linalg.norm(xf)
+    assert abs(ad.residual[-1] - eps) <= 1e-5 * eps
+    assert x.min() >= 0.0
+    # KKT of the constrained problem, from the operator alone
+    g = op.grid(op.degrid(ad.x) - y).numpy()
+    pos = x > 1e-9 * x.max()
+    c = -float(np.mean(g[pos]))
+    assert c > 0
+    assert np.max(np.abs(g[pos] + c)) <= 1e-4 * c
+    assert np.min(g[~pos] + c) >= -1e-4 * c
