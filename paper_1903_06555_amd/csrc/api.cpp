@@ -130,14 +130,13 @@ wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
         c->planned = false;
         return fail(WSP_ESUPPORT, "DDE convolution: J_D x max J_p' complex values exceed 64 KiB");
     }
+    if (support_err & 4) {
+        c->planned = false;
+        return fail(WSP_EINVAL, "w-plane lattice above 2^31 sample pairs: raise plane_dq or plane_dw");
+    }
     if (c->g.planes) {
-        bool too_large = false;
-        e = plane_setup(c, s, &too_large);
-        if (e != hipSuccess) return hip_fail(e, "w-plane layout");
-        if (too_large) {
-            c->planned = false;
-            return fail(WSP_EINVAL, "w-plane lattice above 2^31 sample pairs: raise plane_dq or plane_dw");
-        }
+        e = plane_setup(c, s);
+        if (e != hipSuccess) return hip_fail(e, "w-plane records");
     }
     hipfftResult fr = make_row_plans(c);
     if (fr != HIPFFT_SUCCESS) {

@@ -278,6 +278,7 @@ struct TileArgs {
     int n_items;
     int tile_bits;
     int G;
+    const int32_t *itile;       // items grouped by tile (for the split-tile reduction)
     // w-plane mode: per-entry plane records (work-list order) and the lattice
     const int4 *prec;
     const float *ptw;
@@ -927,18 +928,19 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
     for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(lrow0 + r) * kTile + lane];
 }
 
-// Sum the partial tiles of each tile shared by several items, in item order
-// (deterministic), and store the result in the grid.
+// Sum the partial tiles of each tile shared by several items, in the order of
+// the tile's items (deterministic), and store the result in the grid.
 template <bool kFP64>
 __global__ __launch_bounds__(256) void k_reduce_tiles(const int32_t *__restrict__ mt_first,
                                                       typename Types<kFP64>::C *grids, TileArgs t) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
+    // positions a .. b - 1 of t.itile are the tile's items; their slots are consecutive
     const int a = mt_first[blockIdx.x];
-    const uint32_t key = t.item_key[a];
+    const uint32_t key = t.item_key[t.itile[a]];
     int b = a + 1;
-    while (b < t.n_items && t.item_key[b] == key) ++b;
-    const int slot0 = t.item_slot[a];
+    while (b < t.n_items && t.item_key[t.itile[b]] == key) ++b;
+    const int slot0 = t.item_slot[t.itile[a]];
     const int tmask = (1 << t.tile_bits) - 1;
     const int tx = key & tmask, ty = (key >> t.tile_bits) & tmask;
     const int k = key >> (2 * t.tile_bits);
@@ -1034,6 +1036,7 @@ hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
 }
 
 void set_plane_args(const wsp_ctx *c, TileArgs *ta) {
+    ta->itile = c->plan.itile;
     if (!c->g.planes) return;
     ta->prec = c->plan.prec;
     ta->ptw = c->plan.ptw;

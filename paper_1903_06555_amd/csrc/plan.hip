@@ -310,19 +310,44 @@ __global__ void k_entry_records(const int32_t *__restrict__ idx_sorted, const in
     wrec[s] = make_int4((int)(uint32_t)first, (int)(first >> 32), en.z, en.x);
 }
 
-// (stack, tile) key in the high 32 bits, the pair row floor(|w_eff| / dw) of
-// the entry's visibility in the low 32 (w-plane kernels).
+// w-plane kernels: sort key band | (stack, tile) key | pair row, with the pair
+// row j = floor(|w_eff| / dw) of the entry's visibility and band =
+// j / band_rows (8, 32 and 24 bits).
 __global__ void k_entry_wkey(const uint32_t *__restrict__ keys, const int4 *__restrict__ ent,
-                             const double *__restrict__ weff, double inv_dw, int64_t E, uint64_t *k64) {
+                             const double *__restrict__ weff, double inv_dw, int band_rows, int64_t E,
+                             uint64_t *k64) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
-    const double a = fmin(floor(fabs(weff[ent[e].x]) * inv_dw), 4294967295.0);
-    k64[e] = ((uint64_t)keys[e] << 32) | (uint64_t)a;
+    const double a = fmin(floor(fabs(weff[ent[e].x]) * inv_dw), 16777215.0);
+    const uint64_t j = (uint64_t)a;
+    uint64_t band = j / (uint64_t)band_rows;
+    band = band > 255 ? 255 : band;
+    k64[e] = (band << 56) | ((uint64_t)keys[e] << 24) | j;
 }
 
-__global__ void k_key_hi32(const uint64_t *__restrict__ k64, int64_t E, uint32_t *keys) {
+__global__ void k_key_mid32(const uint64_t *__restrict__ k64, int64_t E, uint32_t *keys) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < E) keys[e] = (uint32_t)(k64[e] >> 32);
+    if (e < E) keys[e] = (uint32_t)(k64[e] >> 24);
+}
+
+// Items grouped by tile (positions i of the stable key sort): sole flags,
+// partial-slot demand and the first position of each split tile.
+__global__ void k_group_flags(const uint32_t *__restrict__ ks, const int32_t *__restrict__ itile, int n,
+                              uint8_t *sole, int *shared_pos, uint8_t *tile_head) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool first = i == 0 || ks[i] != ks[i - 1];
+    const bool last = i == n - 1 || ks[i] != ks[i + 1];
+    const bool multi = !(first && last);
+    sole[itile[i]] = multi ? 0 : 1;
+    shared_pos[i] = multi ? 1 : 0;
+    tile_head[i] = (multi && first) ? 1 : 0;
+}
+
+__global__ void k_scatter_slot(const int32_t *__restrict__ itile, const int *__restrict__ pos, int n,
+                               int32_t *slot) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) slot[itile[i]] = pos[i];
 }
 
 __global__ void k_entry_work(const uint32_t *__restrict__ keys_sorted,
@@ -452,7 +477,8 @@ void free_sorted_plan(Plan &pl) {
     pl.n_items = 0;
     hipFree(pl.item_slot);
     hipFree(pl.mt_first);
-    pl.item_slot = pl.mt_first = nullptr;
+    hipFree(pl.itile);
+    pl.item_slot = pl.mt_first = pl.itile = nullptr;
     pl.n_multi = pl.n_mtiles = 0;
     hipFree(pl.plane_off);
     hipFree(pl.prec);
@@ -494,11 +520,12 @@ __global__ void k_plane_records(const int32_t *__restrict__ idx_sorted, const in
                  &prec[s], &ptw[s]);
 }
 
-// Lattice layout for the planned visibilities (host arithmetic in FP64) and
-// the per-entry plane records.  Pair row j serves |w_eff| in [j dw, (j + 1) dw):
-// its supports are at most J_p((j + 1) dw), whose taps lie within
-// J_p / sqrt(2) cells of the visibility.
-hipError_t plane_setup(wsp_ctx *c, hipStream_t s, bool *too_large) {
+// Lattice layout for the planned visibilities (host arithmetic in FP64).
+// Pair row j serves |w_eff| in [j dw, (j + 1) dw): its supports are at most
+// J_p((j + 1) dw), whose taps lie within J_p / sqrt(2) cells of the
+// visibility.  Also chooses the bands of the work order (below), so that the
+// lattice rows in use at a time stay in cache.
+hipError_t plane_layout(wsp_ctx *c, hipStream_t s, bool *too_large) {
     Plan &pl = c->plan;
     const Geom &g = c->g;
     *too_large = false;
@@ -540,19 +567,34 @@ hipError_t plane_setup(wsp_ctx *c, hipStream_t s, bool *too_large) {
     }
     pl.n_pairs = n_pairs;
     pl.table_len = tot;
+    // a lattice that fits the last-level cache needs no bands (they would only
+    // add items and partial tiles); a larger one is cut into bands of about
+    // one XCD's L2 (4 MiB), at most 255
+    const int64_t bytes = tot * 16, band_bytes = (int64_t)4 << 20;
+    int64_t nbands = bytes <= ((int64_t)64 << 20) ? 1 : (bytes + band_bytes - 1) / band_bytes;
+    nbands = nbands > 255 ? 255 : nbands;
+    pl.band_rows = (int)((n_pairs + nbands - 1) / nbands);
     e = dalloc(&pl.plane_off, (size_t)n_pairs + 1);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pl.plane_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // off[] is released on return
+    return e;
+}
+
+// Per-entry plane records (work-list order), after the work lists.
+hipError_t plane_setup(wsp_ctx *c, hipStream_t s) {
+    Plan &pl = c->plan;
+    const Geom &g = c->g;
     const int64_t E = pl.n_entries;
-    if (e == hipSuccess) e = dalloc(&pl.prec, (size_t)(E > 0 ? E : 1));
+    hipError_t e = dalloc(&pl.prec, (size_t)(E > 0 ? E : 1));
     if (e == hipSuccess) e = dalloc(&pl.ptw, (size_t)(E > 0 ? E : 1));
     if (e == hipSuccess && E > 0) {
         hipLaunchKernelGGL(k_plane_records, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent_sorted, pl.ent,
-                           pl.ux, pl.vx, pl.weff, pl.plane_off, n_pairs, g.plane_inv_dw, E, pl.prec,
+                           pl.ux, pl.vx, pl.weff, pl.plane_off, pl.n_pairs, g.plane_inv_dw, E, pl.prec,
                            pl.ptw);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // off[] is released on return
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
 }
 
@@ -618,27 +660,29 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     int key_bits = 2 * tile_bits + stack_bits;
     key_bits = key_bits > 0 ? key_bits : 1;
     if (g.planes) {
-        // w-plane kernels: within a tile, entries in order of their visibility's
-        // lattice pair row, so the wavefronts working on neighbouring entries
-        // read the same lattice rows (cache reuse instead of one row each)
+        // w-plane kernels: entries in bands of |w_eff| (each band's lattice rows
+        // fit an XCD's L2; one band when the whole lattice fits the last-level
+        // cache), within a band by tile, within a tile by lattice pair row, so
+        // concurrent blocks and neighbouring wavefronts read the same lattice
+        // rows.  A tile then has one item per band.
         uint64_t *k64 = nullptr, *k64s = nullptr;
         WSP_ESTEP(dalloc(&k64, E));
         hipError_t e2 = dalloc(&k64s, E);
         if (e2 == hipSuccess) {
             hipLaunchKernelGGL(k_entry_wkey, dim3(grid1d(E, 256)), dim3(256), 0, s, keys, pl.ent, pl.weff,
-                               g.plane_inv_dw, E, k64);
+                               g.plane_inv_dw, pl.band_rows, E, k64);
             e2 = hipGetLastError();
         }
         size_t need64 = 0;
         if (e2 == hipSuccess)
             e2 = hipcub::DeviceRadixSort::SortPairs(nullptr, need64, k64, k64s, iota, pl.ent_sorted, (int)E,
-                                                    0, 32 + key_bits, s);
+                                                    0, 64, s);
         if (e2 == hipSuccess) e2 = scratch(need64);
         if (e2 == hipSuccess)
             e2 = hipcub::DeviceRadixSort::SortPairs(tmp, need64, k64, k64s, iota, pl.ent_sorted, (int)E, 0,
-                                                    32 + key_bits, s);
+                                                    64, s);
         if (e2 == hipSuccess) {
-            hipLaunchKernelGGL(k_key_hi32, dim3(grid1d(E, 256)), dim3(256), 0, s, k64s, E, keys_sorted);
+            hipLaunchKernelGGL(k_key_mid32, dim3(grid1d(E, 256)), dim3(256), 0, s, k64s, E, keys_sorted);
             e2 = hipGetLastError();
         }
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);  // before k64 / k64s are released
@@ -698,24 +742,50 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     hipLaunchKernelGGL(k_item_info, dim3(grid1d(nsel, 256)), dim3(256), 0, s, pl.item_start, nsel,
                        E, keys_sorted, head, pl.item_key, pl.item_sole, pl.item_start + nsel);
     WSP_ESTEP(hipGetLastError());
-    // items of tiles split over several items write partial tiles to slots
-    // (in item order); the tiles' first items index the reduction
+    // items of tiles split over several items write partial tiles to slots;
+    // a tile's items are grouped by a stable sort on the key (the identity
+    // when the work order is by tile), slots follow that grouping, and the
+    // split tiles' first positions index the reduction
     {
-        int *shared_item = nullptr;
-        WSP_ESTEP(dalloc(&shared_item, nsel + 1));
+        int *shared_pos = nullptr, *slot_pos = nullptr;
+        uint32_t *iks = nullptr;
+        int32_t *iiota = nullptr;
+        WSP_ESTEP(dalloc(&shared_pos, nsel + 1));
+        WSP_ESTEP(dalloc(&slot_pos, nsel + 1));
+        WSP_ESTEP(dalloc(&iks, nsel));
+        WSP_ESTEP(dalloc(&iiota, nsel));
+        WSP_ESTEP(dalloc(&pl.itile, nsel));
         WSP_ESTEP(dalloc(&pl.item_slot, nsel + 1));
         WSP_ESTEP(dalloc(&pl.mt_first, nsel + 1));
         uint8_t *tile_head = ihead;  // reuse (E >= nsel)
-        hipLaunchKernelGGL(k_multi_flags, dim3(grid1d(nsel, 256)), dim3(256), 0, s, pl.item_key,
-                           pl.item_sole, nsel, shared_item, tile_head);
-        e = hipMemsetAsync(shared_item + nsel, 0, sizeof(int), s);
+        hipLaunchKernelGGL(k_iota, dim3(grid1d(nsel, 256)), dim3(256), 0, s, iiota, (int64_t)nsel);
+        e = hipGetLastError();
         if (e == hipSuccess) {
             need = 0;
-            e = hipcub::DeviceScan::ExclusiveSum(nullptr, need, shared_item, pl.item_slot, nsel + 1, s);
+            e = hipcub::DeviceRadixSort::SortPairs(nullptr, need, pl.item_key, iks, iiota, pl.itile, nsel, 0,
+                                                   key_bits, s);
         }
         if (e == hipSuccess) e = scratch(need);
         if (e == hipSuccess)
-            e = hipcub::DeviceScan::ExclusiveSum(tmp, need, shared_item, pl.item_slot, nsel + 1, s);
+            e = hipcub::DeviceRadixSort::SortPairs(tmp, need, pl.item_key, iks, iiota, pl.itile, nsel, 0,
+                                                   key_bits, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_group_flags, dim3(grid1d(nsel, 256)), dim3(256), 0, s, iks, pl.itile, nsel,
+                               pl.item_sole, shared_pos, tile_head);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemsetAsync(shared_pos + nsel, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            need = 0;
+            e = hipcub::DeviceScan::ExclusiveSum(nullptr, need, shared_pos, slot_pos, nsel + 1, s);
+        }
+        if (e == hipSuccess) e = scratch(need);
+        if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, need, shared_pos, slot_pos, nsel + 1, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_scatter_slot, dim3(grid1d(nsel, 256)), dim3(256), 0, s, pl.itile, slot_pos,
+                               nsel, pl.item_slot);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess) {
             need = 0;
             e = hipcub::DeviceSelect::Flagged(nullptr, need, counting, tile_head, pl.mt_first, d_nsel,
@@ -728,12 +798,15 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
         int nmt = 0, nmulti = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&nmt, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(&nmulti, pl.item_slot + nsel, sizeof(int), hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(&nmulti, slot_pos + nsel, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(pl.mt_first + nmt, &nsel, sizeof(int), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        hipFree(shared_item);
+        hipFree(shared_pos);
+        hipFree(slot_pos);
+        hipFree(iks);
+        hipFree(iiota);
         WSP_ESTEP(e);
         pl.n_mtiles = nmt;
         pl.n_multi = nmulti;
@@ -882,6 +955,16 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     pl.max_jp = mx;
     pl.tile_bits = tile_bits;
     cleanup();
+    if (g.planes) {
+        // the lattice layout sets the bands of the work order
+        bool too_large = false;
+        hipError_t e2 = plane_layout(c, s, &too_large);
+        if (e2 != hipSuccess) return e2;
+        if (too_large) {
+            *support_err |= 4;
+            return hipSuccess;
+        }
+    }
     return make_entries(pl, g, tile_bits, s);
 #undef WSP_STEP
 }

@@ -115,12 +115,15 @@ struct Plan {
     int32_t *item_slot = nullptr; // [n_items] partial-tile slot of a shared tile's item
     int n_multi = 0;              // items whose tile is split over several items
     int n_mtiles = 0;             // tiles split over several items
-    int32_t *mt_first = nullptr;  // [n_mtiles + 1] first item of each split tile (+ n_items)
+    int32_t *itile = nullptr;     // [n_items] items grouped by tile (stable): a tile's items need
+                                  // not be adjacent in the work order
+    int32_t *mt_first = nullptr;  // [n_mtiles + 1] first position in itile of each split tile (+ n_items)
     int tile_bits = 0;
     // w-plane mode.  Pair row j (j < n_pairs) holds float4 (T[j, i], T[j+1, i])
     // for i < plane_off[j + 1] - plane_off[j]; a visibility with
     // j dw <= |w_eff| < (j + 1) dw reads row j.
     int n_pairs = 0;
+    int band_rows = 0;            // pair rows per band of the work order (see make_entries)
     int64_t table_len = 0;        // float4 elements of the lattice
     int64_t *plane_off = nullptr; // [n_pairs + 1] device
     int4 *prec = nullptr;         // [n_entries] in work-list order: {first float4 of the pair row,
@@ -198,7 +201,7 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K,
 hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err);
 void free_sorted_plan(Plan &pl);
 
-hipError_t plane_setup(wsp_ctx *c, hipStream_t s, bool *too_large);
+hipError_t plane_setup(wsp_ctx *c, hipStream_t s);
 
 // build.hip
 hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s);
