@@ -383,25 +383,12 @@ __global__ void k_item_head(const int64_t *__restrict__ incl, const int64_t *__r
 }
 
 __global__ void k_item_info(const int32_t *__restrict__ item_start, int n_items, int64_t E,
-                            const uint32_t *__restrict__ keys_sorted,
-                            const uint8_t *__restrict__ head, uint32_t *item_key, uint8_t *sole,
+                            const uint32_t *__restrict__ keys_sorted, uint32_t *item_key,
                             int32_t *item_start_out_last) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
-    int s = item_start[i];
-    int64_t next = (i + 1 < n_items) ? item_start[i + 1] : E;
-    item_key[i] = keys_sorted[s];
-    sole[i] = (head[s] && (next == E || head[next])) ? 1 : 0;
+    item_key[i] = keys_sorted[item_start[i]];
     if (i == n_items - 1) *item_start_out_last = (int32_t)E;
-}
-
-__global__ void k_multi_flags(const uint32_t *__restrict__ item_key,
-                              const uint8_t *__restrict__ sole, int n, int *shared_item,
-                              uint8_t *tile_head) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    shared_item[i] = sole[i] ? 0 : 1;
-    tile_head[i] = (!sole[i] && (i == 0 || item_key[i] != item_key[i - 1])) ? 1 : 0;
 }
 
 }  // namespace
@@ -740,7 +727,7 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     WSP_ESTEP(dalloc(&pl.item_key, nsel));
     WSP_ESTEP(dalloc(&pl.item_sole, nsel));
     hipLaunchKernelGGL(k_item_info, dim3(grid1d(nsel, 256)), dim3(256), 0, s, pl.item_start, nsel,
-                       E, keys_sorted, head, pl.item_key, pl.item_sole, pl.item_start + nsel);
+                       E, keys_sorted, pl.item_key, pl.item_start + nsel);
     WSP_ESTEP(hipGetLastError());
     // items of tiles split over several items write partial tiles to slots;
     // a tile's items are grouped by a stable sort on the key (the identity
