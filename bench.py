@@ -36,7 +36,7 @@ def log(msg: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mwa_1024_single_stack")
     ap.add_argument("--precision", default=None, help="override: fp32_fp64phase or fp64")
