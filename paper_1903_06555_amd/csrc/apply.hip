@@ -367,12 +367,17 @@ __device__ __forceinline__ double bcast(double x, int l) {
 
 // Batches of U x 64 consecutive taps of a run: 8 while at least 6 blocks of
 // 64 taps are left, then 4, 2, 1, so a run's tail issues few redundant loads
-// and the bulk keeps 8 loads per lane in flight.
-template <typename F>
+// and the bulk keeps 8 loads per lane in flight.  kWide (w-plane kernels,
+// whose lattice lookups are latency-bound) adds batches of 16 while at least
+// 12 blocks are left.
+template <bool kWide = false, typename F>
 __device__ __forceinline__ void for_batches(int kbeg, int kend, F &&f) {
     for (int k0 = kbeg; k0 < kend;) {
         const int nb = (kend - k0 + 63) >> 6;  // uniform over the wavefront
-        if (nb >= 6) {
+        if (kWide && nb >= 12) {
+            f(k0, std::integral_constant<int, 16>());
+            k0 += 1024;
+        } else if (nb >= 6) {
             f(k0, std::integral_constant<int, 8>());
             k0 += 512;
         } else if (nb >= 3) {
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void k_degrid_tiles(const typename Types<
             const int ntap = nr * nc;
             const int cell0 = ly0 * kTile + lx0;  // tile cell of sub-block tap 0
             R ar = 0, ai = 0;
-            for_batches(0, ntap, [&](int k0, auto ucount) {
+            for_batches<kPlanes>(0, ntap, [&](int k0, auto ucount) {
                 constexpr int U = decltype(ucount)::value;
                 C K[U];
                 int li[U];
@@ -722,7 +727,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_tiles(con
                 const int kbeg = (lo - ly0) * nc, kend = (hi - ly0) * nc;
                 const float inv_nc = recip_nc(nc);
                 const int cell0 = (ly0 - part * kRows) * kTile + lx0;  // LDS cell of sub-block tap 0
-                for_batches(kbeg, kend, [&](int k0, auto ucount) {
+                for_batches<kPlanes>(kbeg, kend, [&](int k0, auto ucount) {
                     constexpr int U = decltype(ucount)::value;
                     C K[U], z[U];
                     int li[U];
