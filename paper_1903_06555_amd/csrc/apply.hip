@@ -499,7 +499,9 @@ __global__ __launch_bounds__(kThreads) void k_degrid_small(const typename Types<
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     constexpr int kPer = 64 / kGroup;  // entries per wavefront pass
-    constexpr int kU = 8;              // load slots per lane
+    // load slots per lane; w-plane kernels use 4 (their lookups hit a
+    // cache-resident lattice, and the extra resident wavefronts hide more)
+    constexpr int kU = kPlanes ? 4 : 8;
     __shared__ C tile[kTile * kTile];
     __shared__ int s_geo[kChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
     __shared__ int s_idx[kChunk];
@@ -792,6 +794,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                                                                         const typename Types<kFP64>::C *__restrict__ yw,
                                                                         typename Types<kFP64>::C *grids, TileArgs t) {
     using C = typename Types<kFP64>::C;
+    constexpr int kS = kPlanes ? kSlots / 2 : kSlots;  // slots (4 for w-plane kernels, as in degrid)
     constexpr int kRows = kTile / kH;  // tile rows of this block
     __shared__ C tile[kRows * kTile + 1];  // + a spare cell for lanes without a tap
     __shared__ int s_geo[kGChunk];  // nc | nr << 8 | lx0 << 16 | ly0 << 24
@@ -851,12 +854,12 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
             int k0 = 0, kend = 0, kbeg = 0, nc = 1, cell0 = 0, yl = 0;
             float inv_nc = 1.0f;
             while (hits || k0 < kend) {
-                C K[kSlots];
-                int li[kSlots], ys[kSlots];
-                PlaneLoad L[kPlanes ? kSlots : 1];
-                float sws[kPlanes ? kSlots : 1], sgs[kPlanes ? kSlots : 1];
+                C K[kS];
+                int li[kS], ys[kS];
+                PlaneLoad L[kPlanes ? kS : 1];
+                float sws[kPlanes ? kS : 1], sgs[kPlanes ? kS : 1];
 #pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl) {
+                for (int sl = 0; sl < kS; ++sl) {
                     li[sl] = kRows * kTile;  // lanes without a tap update the spare cell by zero
                     if (k0 >= kend && hits) {  // next entry with rows in the band
                         const int l = __builtin_ctzll(hits);
@@ -902,7 +905,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
                     }
                 }
 #pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl) {
+                for (int sl = 0; sl < kS; ++sl) {
                     if constexpr (kPlanes) {
                         const float2 v = plane_value(L[sl], sws[sl], sgs[sl]);
                         K[sl].x = v.x;
