@@ -152,3 +152,36 @@ def test_fullsize_sampled_dde():
         assert err <= 1e-5
     finally:
         op.close()
+
+
+def test_dde_build_in_parts_and_after_restack():
+    """A part-wise build gives the same taps; DDE kernels survive wsp_set_stacks."""
+    geom = wkernel.Geometry(n=N, fov=FOV)
+    uvw = syn.uniform_box_uvw(900, u_max=40.0, w_max=20.0, seed=120)
+    du, dv = random_dde(uvw.shape[0], 3, 121)
+    params = wsp.make_params(N, FOV, n_stacks=2, fold=True, precision="fp64", dde_support=3)
+    a = wsp.Operator(params, uvw, build=False)
+    b = wsp.Operator(params, uvw, build=False)
+    try:
+        labels, centres, _ = a.stacks()
+        b.set_stacks(labels, centres)
+        a.set_dde(du, dv)
+        b.set_dde(du, dv)
+        a.build()
+        seen = []
+        b.build(part=250, progress=lambda d, n: seen.append(d))
+        assert seen == [250, 500, 750, 900]
+        x = torch.from_numpy(syn.point_source_sky(N, 8, "gaussian", seed=122, margin=4))
+        assert torch.equal(a.degrid(x), b.degrid(x))
+        # re-plan with another assignment: the DDE kernels are kept, the taps rebuilt
+        other = np.zeros(uvw.shape[0], dtype=np.int32)
+        b.set_stacks(other, np.array([0.0, 5.0]))
+        b.build()
+        ref = operator.StackedOperator(geom, uvw, labels=other, centres=np.array([0.0, 5.0]), fold=True,
+                                       kernel_fn=dde.DDEKernels(du, dv), extra_support=2)
+        y = b.degrid(x).cpu().numpy()
+        y_ref = ref.forward(x.numpy())
+        assert np.linalg.norm(y - y_ref) <= 1e-5 * np.linalg.norm(y_ref)
+    finally:
+        a.close()
+        b.close()
