@@ -46,11 +46,13 @@ constexpr int64_t kBuildBatch = 65536;    // visibilities per partition batch
 // band-limited (J0(2 pi r q) with r <= alpha / 2): where fewer uniform samples
 // q = s h cover a visibility's taps than it has taps, the quadrature runs on
 // the samples and each tap is interpolated from the 10 samples around it
-// (Lagrange, FP64; K(-q) = K(q) mirrors the first ones).  With h = 1/8 cell
-// the interpolation error is ~2e-9 of the kernel peak (measured against the
-// oracle at |w| up to 250), far below the quadrature tolerance.
-constexpr double kSampleStep = 0.125;
-constexpr double kInvSampleStep = 8.0;
+// (Lagrange, FP64; K(-q) = K(q) mirrors the first ones).  Measured against
+// the oracle at |w| up to 480, the interpolation error is ~3e-9 of the kernel
+// peak with h = 1/8 cell (the FP64 path) and ~6e-8 with h = 1/6 (the FP32
+// path, whose own rounding is ~1e-7): both far below the 1e-6 quadrature
+// tolerance.
+constexpr double kSampleStep64 = 0.125, kInvSampleStep64 = 8.0;
+constexpr double kSampleStep32 = 1.0 / 6.0, kInvSampleStep32 = 6.0;
 constexpr int kStencil = 10;
 
 struct PointSet {
@@ -59,15 +61,16 @@ struct PointSet {
     bool sampled;
 };
 
-// q_max over the J_p x J_p taps at offsets (ux - col, vx - row)
-__device__ __forceinline__ PointSet point_set(double ux, double vx, int jp) {
+// q_max over the J_p x J_p taps at offsets (ux - col, vx - row); samples at
+// q = s step
+__device__ __forceinline__ PointSet point_set(double ux, double vx, int jp, double step, double inv_step) {
     const double cu = fmax(fabs(ux), fabs(ux - (double)(jp - 1)));
     const double cv = fmax(fabs(vx), fabs(vx - (double)(jp - 1)));
     const double qmax = sqrt(cu * cu + cv * cv);
     // samples 0 .. ns - 1 hold every tap's stencil floor(q / h) - 4 .. floor(q / h) + 5
-    const int64_t ns = (int64_t)floor(qmax * kInvSampleStep) + kStencil / 2 + 1;
+    const int64_t ns = (int64_t)floor(qmax * inv_step) + kStencil / 2 + 1;
     const int64_t nt = (int64_t)jp * jp;
-    if (ns < nt) return {(double)(ns - 1) * kSampleStep, ns, true};
+    if (ns < nt) return {(double)(ns - 1) * step, ns, true};
     return {qmax, nt, false};
 }
 
@@ -78,6 +81,7 @@ struct BuildArgs {
     int n_pairs;
     double plane_dq, plane_dw;
     float2 *table2;
+    double sstep, inv_sstep;  // radial sample step of the precision path
     // DDE convolution (g.dde_h > 0): per-visibility kernels, caller order, and
     // the sorted -> caller permutation
     const void *dde_u, *dde_v;
@@ -121,7 +125,7 @@ __device__ __forceinline__ Target build_target(const BuildArgs &A, int64_t b) {
         return {j, (double)j * A.plane_dw, plane_points(A, j)};
     }
     const int p = A.border[b];
-    return {p, A.weff[p], point_set(A.ux[p], A.vx[p], A.jp[p])};
+    return {p, A.weff[p], point_set(A.ux[p], A.vx[p], A.jp[p], A.sstep, A.inv_sstep)};
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
     const int jp = planes ? 1 : A.jp[p];
     const PointSet ps = tg.ps;
     const int64_t ntap = ps.npts;
-    const double sstep = planes ? A.plane_dq : kSampleStep;
+    const double sstep = planes ? A.plane_dq : A.sstep;
     const int P = npan[i];
     const float *bnd = part + (int64_t)i * (kMaxPanels + 2);
     const int64_t chunk = (int64_t)kWave * kTapsPerLane;
@@ -627,7 +631,7 @@ __global__ __launch_bounds__(256) void k_interp(BuildArgs A, int64_t batch0,
     const int p = A.border[batch0 + i];
     const double ux = A.ux[p], vx = A.vx[p];
     const int jp = A.jp[p];
-    const PointSet ps = point_set(ux, vx, jp);
+    const PointSet ps = point_set(ux, vx, jp, A.sstep, A.inv_sstep);
     if (!ps.sampled) return;  // uniform over the block
     const double2 *smp = samples + samp_off[i];
     const int64_t off = A.tap_off[p];
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(256) void k_interp(BuildArgs A, int64_t batch0,
     for (int64_t t = threadIdx.x; t < ntap; t += blockDim.x) {
         const int row = (int)(t / jp), col = (int)(t - (int64_t)row * jp);
         const double du = ux - (double)col, dv = vx - (double)row;
-        const double x = sqrt(du * du + dv * dv) * kInvSampleStep;
+        const double x = sqrt(du * du + dv * dv) * A.inv_sstep;
         const int s0 = (int)floor(x) - (kStencil / 2 - 1);
         const double u = x - (double)s0;  // in [4, 5): position inside the stencil
         // Lagrange basis on the nodes 0 .. 9: l_k(u) = c_k prod_{j != k} (u - j),
@@ -854,6 +858,9 @@ BuildArgs common_args(wsp_ctx *c) {
     A.tol = c->p.quad_abs_tol > 0.0 ? c->p.quad_abs_tol : c->p.quad_rel_tol;
     A.max_panels = c->p.quad_max_panels;
     A.stats = c->plan.stats;
+    const bool fp64 = c->p.precision == WSP_FP64;
+    A.sstep = fp64 ? kSampleStep64 : kSampleStep32;
+    A.inv_sstep = fp64 ? kInvSampleStep64 : kInvSampleStep32;
     return A;
 }
 
