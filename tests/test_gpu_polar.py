@@ -130,3 +130,32 @@ def test_fullsize_sampled_pol():
         assert eq <= 1e-5 and eu <= 1e-5
     finally:
         op.close()
+
+
+@pytest.mark.parametrize("mode", ["planes", "dde"])
+def test_pol_with_plane_and_dde_kernels(mode):
+    """The polarised entry points run the Stokes pipeline of any kernel mode."""
+    uvw = syn.uniform_box_uvw(700, u_max=40.0, w_max=20.0, seed=130)
+    m = uvw.shape[0]
+    if mode == "planes":
+        params = wsp.make_params(N, FOV, n_stacks=2, fold=True, kernels="planes")
+        op = wsp.Operator(params, uvw)
+    else:
+        params = wsp.make_params(N, FOV, n_stacks=2, fold=True, precision="fp64", dde_support=3)
+        op = wsp.Operator(params, uvw, build=False)
+        rng = np.random.default_rng(131)
+        d = (rng.normal(size=(m, 3)) + 1j * rng.normal(size=(m, 3))) / 3
+        op.set_dde(d, d[::-1].copy())
+        op.build()
+    try:
+        q = torch.from_numpy(syn.point_source_sky(N, 8, "gaussian", seed=132, margin=4))
+        u = torch.from_numpy(syn.point_source_sky(N, 8, "gaussian", seed=133, margin=4))
+        yp = op.degrid_pol(q, u)
+        ys = op.degrid(q) + 1j * op.degrid(u)
+        assert torch.allclose(yp, ys, rtol=0, atol=1e-6 * float(ys.abs().max()))
+        yr = torch.from_numpy(syn.random_vis(m, seed=134))
+        qa, ua = op.grid_pol(yr)
+        assert torch.allclose(qa, op.grid(yr), rtol=0, atol=1e-6 * float(qa.abs().max()))
+        assert torch.allclose(ua, op.grid(-1j * yr), rtol=0, atol=1e-6 * float(ua.abs().max()))
+    finally:
+        op.close()
