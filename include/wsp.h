@@ -205,6 +205,20 @@ wsp_status wsp_build_kernels(wsp_ctx *ctx, void *stream);
  * wsp_build_kernels, WSP_EINVAL (range), WSP_ESTATE (out of order). */
 wsp_status wsp_build_kernels_part(wsp_ctx *ctx, int64_t first, int64_t count, void *stream);
 
+/* wsp_build_kernels for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same taps, bit for bit, but the build
+ * temporaries (quadrature partitions, radial samples, scan storage) live in
+ * a static device array of 64 MiB that each GPU using the library holds until
+ * the process ends, instead of memory the build allocates.  Visibilities are
+ * processed in batches sized so that the worst case of a batch fits.  The
+ * call allocates nothing; the kernel taps still go to the caller's bound
+ * buffer.  Every call on one GPU shares that GPU's array: calls that overlap
+ * in time on one GPU (other contexts or threads) race and must be serialised
+ * by the caller.  Blocks until complete.  Errors: as wsp_build_kernels, and
+ * WSP_ENOMEM_BINDING if one visibility's temporaries exceed the array. */
+wsp_status wsp_build_kernels_noalloc(wsp_ctx *ctx, void *stream);
+
 /* Quadrature statistics of the last build: total panels, and visibilities
  * whose panel cap was reached.  Errors: WSP_ESTATE. */
 wsp_status wsp_quad_stats(const wsp_ctx *ctx, int64_t *panels, int64_t *capped);

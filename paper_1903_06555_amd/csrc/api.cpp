@@ -314,8 +314,14 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     if (p.device >= ndev) return fail(WSP_EINVAL, "no such device");
     HIP_OR_FAIL(hipSetDevice(p.device), "hipSetDevice");
 
+    // the device address of this device's static build workspace (looked up
+    // once per device, with the device current)
+    void *static_ws = nullptr;
+    HIP_OR_FAIL(static_scratch_init(p.device, &static_ws), "hipGetSymbolAddress (static build workspace)");
+
     wsp_ctx *c = new (std::nothrow) wsp_ctx();
     if (!c) return fail(WSP_EHIP, "out of host memory");
+    c->static_scratch = static_ws;
     c->p = p;
     c->g = g;
     c->device = p.device;
@@ -543,7 +549,9 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
     return WSP_OK;
 }
 
-wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void *stream) {
+namespace {
+// Build parts [first, first + count); ws == nullptr allocates the temporaries.
+wsp_status build_part(wsp_ctx *c, int64_t first, int64_t count, void *stream, void *ws, size_t ws_bytes) {
     if (!c) return fail(WSP_EINVAL, "null argument");
     if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
     if (!c->bound) return fail(WSP_ENOMEM_BINDING, "wsp_bind_memory first");
@@ -555,14 +563,14 @@ wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void
     if (c->g.planes) {
         // the lattice serves every visibility: built by the first part
         if (first == 0) {
-            HIP_OR_FAIL(launch_plane_build(c, s), "w-plane build");
+            HIP_OR_FAIL(launch_plane_build(c, s, ws, ws_bytes), "w-plane build");
         } else {
             c->built_upto = first + count;
             c->built = c->built_upto == c->plan.m;
             return WSP_OK;
         }
     } else {
-        HIP_OR_FAIL(launch_build(c, first, count, s), "build");
+        HIP_OR_FAIL(launch_build(c, first, count, s, ws, ws_bytes), "build");
     }
     unsigned long long st[2] = {0, 0};
     HIP_OR_FAIL(hipMemcpyAsync(st, c->plan.stats, sizeof(st), hipMemcpyDeviceToHost, s), "stats");
@@ -576,6 +584,24 @@ wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void
         return WSP_WARN_QUAD_MAXEVAL;
     }
     return WSP_OK;
+}
+}  // namespace
+
+wsp_status wsp_build_kernels_part(wsp_ctx *c, int64_t first, int64_t count, void *stream) {
+    return build_part(c, first, count, stream, nullptr, 0);
+}
+
+wsp_status wsp_build_kernels_noalloc(wsp_ctx *c, void *stream) {
+    if (!c) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    if (!c->static_scratch) return fail(WSP_EHIP, "static build workspace unavailable");
+    if (build_batch_in(c, static_scratch_bytes()) < 1)
+        return fail(WSP_ENOMEM_BINDING, "the build temporaries of one visibility exceed the " +
+                                            std::to_string(static_scratch_bytes() >> 20) +
+                                            " MiB static workspace");
+    c->built_upto = 0;
+    c->built = false;
+    return build_part(c, 0, c->plan.m, stream, c->static_scratch, static_scratch_bytes());
 }
 
 wsp_status wsp_build_kernels(wsp_ctx *c, void *stream) {

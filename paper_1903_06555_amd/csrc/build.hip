@@ -23,6 +23,7 @@
 // sums in FP32, accumulated over the partition in FP64.  FP64 path: all FP64.
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
 #include <type_traits>
 
 #include "wsp_devmath.h"
@@ -750,8 +751,84 @@ __global__ void k_unit_counts(BuildArgs A, int64_t batch0, int nb, int64_t chunk
 
 namespace {
 
+// ---- build workspace -------------------------------------------------------
+// The temporaries of one build batch of B visibilities: the partitions
+// (kMaxPanels + 2 boundaries each), panel counts, per-visibility unit and
+// sample counts with their exclusive scans (and the scans' hipcub storage),
+// and the FP64 radial samples.  They come either from hipMalloc (one
+// allocation per array, freed at the end of the build) or from one region
+// given by the caller of run_build, carved at 256-byte boundaries.
+
+constexpr size_t kWsAlign = 256;
+
+size_t ws_round(size_t x) { return (x + kWsAlign - 1) & ~(kWsAlign - 1); }
+
+// Upper bound on the radial samples of one visibility of support jp: samples
+// are used only below jp^2 points, and their count is floor(q_max / h) + 6
+// with q_max <= jp / sqrt(2) (the visibility sits within half a cell of its
+// support's centre).
+int64_t max_samples_per_vis(int jp, double inv_step) {
+    const int64_t ns = (int64_t)floor((double)jp * 0.70710678118654757 * inv_step) + kStencil / 2 + 2;
+    const int64_t nt = (int64_t)jp * jp;
+    return ns < nt ? ns : nt;
+}
+
+struct WsLayout {
+    size_t part, npan, cnt, scnt, soff, uoff, tmp, tmp2, samples, total;
+};
+
+// Byte layout of the temporaries for batches of B visibilities with at most
+// `samples` radial samples per batch.  The hipcub storage sizes come from
+// hipcub's own size queries (no allocation).
+hipError_t ws_layout(int B, int64_t samples, WsLayout *L) {
+    size_t tmp = 0, tmp2 = 0;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (const int *)nullptr, (int *)nullptr, B + 1);
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2, (const int64_t *)nullptr, (int64_t *)nullptr, B + 1);
+    if (e != hipSuccess) return e;
+    L->part = ws_round(sizeof(float) * (size_t)B * (kMaxPanels + 2));
+    L->npan = ws_round(sizeof(int) * (size_t)B);
+    L->cnt = ws_round(sizeof(int) * (size_t)(B + 1));
+    L->scnt = ws_round(sizeof(int64_t) * (size_t)(B + 1));
+    L->soff = ws_round(sizeof(int64_t) * (size_t)(B + 1));
+    L->uoff = ws_round(sizeof(int) * (size_t)(B + 1));
+    L->tmp = ws_round(tmp > 0 ? tmp : 1);
+    L->tmp2 = ws_round(tmp2 > 0 ? tmp2 : 1);
+    L->samples = ws_round(sizeof(double2) * (size_t)(samples > 0 ? samples : 1));
+    L->total = L->part + L->npan + L->cnt + L->scnt + L->soff + L->uoff + L->tmp + L->tmp2 + L->samples;
+    return hipSuccess;
+}
+
+// Largest radial-sample count a batch of B build slots can need (w-plane
+// samples are written to the lattice directly).
+int64_t batch_samples_bound(const wsp_ctx *c, bool planes, double inv_step, int B) {
+    if (planes) return 0;
+    return (int64_t)B * max_samples_per_vis(c->plan.max_jp, inv_step);
+}
+
+// Batch size of a build that must fit `cap` bytes of workspace (0 if not even
+// one visibility fits).
+hipError_t fitting_batch(const wsp_ctx *c, const BuildArgs &A, int64_t count, size_t cap, int *B_out) {
+    int B = (int)(count < kBuildBatch ? count : kBuildBatch);
+    while (B >= 1) {
+        WsLayout L;
+        hipError_t e = ws_layout(B, batch_samples_bound(c, A.plane_off != nullptr, A.inv_sstep, B), &L);
+        if (e != hipSuccess) return e;
+        if (L.total <= cap) break;
+        // shrink in proportion to the overshoot (at least by one)
+        const int nb = (int)((double)B * (double)cap / (double)L.total * 0.98);
+        B = nb < B ? nb : B - 1;
+    }
+    *B_out = B > 0 ? B : 0;
+    return hipSuccess;
+}
+
 // Phases 1 and 2 over build slots first .. first + count - 1, in batches.
-hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t count, hipStream_t s) {
+// ws == nullptr: the temporaries are allocated with hipMalloc and freed on
+// return.  Otherwise they are carved from [ws, ws + ws_bytes) and nothing is
+// allocated; the batch size is then the largest whose worst case fits.
+hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t count, hipStream_t s,
+                     char *ws = nullptr, size_t ws_bytes = 0) {
     const Plan &pl = c->plan;
     hipError_t e = hipSuccess;
     if (first == 0) {
@@ -759,7 +836,12 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
         if (e != hipSuccess) return e;
     }
     const int64_t end = first + count;
-    const int B = (int)(count < kBuildBatch ? count : kBuildBatch);
+    int B = (int)(count < kBuildBatch ? count : kBuildBatch);
+    if (ws) {
+        e = fitting_batch(c, A, count, ws_bytes, &B);
+        if (e != hipSuccess) return e;
+        if (B < 1) return hipErrorOutOfMemory;
+    }
     float *part = nullptr;
     int *npan = nullptr, *cnt = nullptr, *uoff = nullptr;
     int64_t *scnt = nullptr, *soff = nullptr;
@@ -770,6 +852,7 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
     void *tmp = nullptr;
     size_t tmp_bytes = 0;
     auto cleanup = [&]() {
+        if (ws) return;  // carved from the caller's region: nothing to free
         hipFree(part);
         hipFree(npan);
         hipFree(cnt);
@@ -788,16 +871,42 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
             return e;          \
         }                      \
     } while (0)
-    WSP_BSTEP(hipMalloc(&part, sizeof(float) * (size_t)B * (kMaxPanels + 2)));
-    WSP_BSTEP(hipMalloc(&npan, sizeof(int) * (size_t)B));
-    WSP_BSTEP(hipMalloc(&cnt, sizeof(int) * (size_t)(B + 1)));
-    WSP_BSTEP(hipMalloc(&scnt, sizeof(int64_t) * (size_t)(B + 1)));
-    WSP_BSTEP(hipMalloc(&soff, sizeof(int64_t) * (size_t)(B + 1)));
-    WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2_bytes, scnt, soff, B + 1, s));
-    WSP_BSTEP(hipMalloc(&tmp2, tmp2_bytes));
-    WSP_BSTEP(hipMalloc(&uoff, sizeof(int) * (size_t)(B + 1)));
-    WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, uoff, B + 1, s));
-    WSP_BSTEP(hipMalloc(&tmp, tmp_bytes));
+    if (ws) {
+        WsLayout L;
+        WSP_BSTEP(ws_layout(B, batch_samples_bound(c, A.plane_off != nullptr, A.inv_sstep, B), &L));
+        char *q = ws;
+        part = (float *)q;
+        q += L.part;
+        npan = (int *)q;
+        q += L.npan;
+        cnt = (int *)q;
+        q += L.cnt;
+        scnt = (int64_t *)q;
+        q += L.scnt;
+        soff = (int64_t *)q;
+        q += L.soff;
+        uoff = (int *)q;
+        q += L.uoff;
+        tmp = q;
+        tmp_bytes = L.tmp;
+        q += L.tmp;
+        tmp2 = q;
+        tmp2_bytes = L.tmp2;
+        q += L.tmp2;
+        samples = (double2 *)q;
+        samples_cap = (int64_t)(L.samples / sizeof(double2));
+    } else {
+        WSP_BSTEP(hipMalloc(&part, sizeof(float) * (size_t)B * (kMaxPanels + 2)));
+        WSP_BSTEP(hipMalloc(&npan, sizeof(int) * (size_t)B));
+        WSP_BSTEP(hipMalloc(&cnt, sizeof(int) * (size_t)(B + 1)));
+        WSP_BSTEP(hipMalloc(&scnt, sizeof(int64_t) * (size_t)(B + 1)));
+        WSP_BSTEP(hipMalloc(&soff, sizeof(int64_t) * (size_t)(B + 1)));
+        WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2_bytes, scnt, soff, B + 1, s));
+        WSP_BSTEP(hipMalloc(&tmp2, tmp2_bytes));
+        WSP_BSTEP(hipMalloc(&uoff, sizeof(int) * (size_t)(B + 1)));
+        WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, uoff, B + 1, s));
+        WSP_BSTEP(hipMalloc(&tmp, tmp_bytes));
+    }
     for (int64_t b0 = first; b0 < end; b0 += B) {
         int nb = (int)(end - b0 < B ? end - b0 : B);
         dim3 block(kWave * kWavesPerBlock);
@@ -816,6 +925,11 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
         WSP_BSTEP(hipMemcpyAsync(&nsamp, soff + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         WSP_BSTEP(hipStreamSynchronize(s));  // also: the previous batch no longer uses samples
         if (nsamp > samples_cap) {
+            if (ws) {  // cannot happen: the layout holds the worst case
+                e = hipErrorOutOfMemory;
+                cleanup();
+                return e;
+            }
             hipFree(samples);
             samples = nullptr;
             samples_cap = 0;
@@ -866,7 +980,7 @@ BuildArgs common_args(wsp_ctx *c) {
 
 }  // namespace
 
-hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s) {
+hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s, void *ws, size_t ws_bytes) {
     BuildArgs A = common_args(c);
     const Plan &pl = c->plan;
     A.border = pl.border;
@@ -882,11 +996,11 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s)
     A.dde_u = c->dde_u;
     A.dde_v = c->dde_v;
     A.perm = pl.perm;
-    return run_build(c, A, first, count, s);
+    return run_build(c, A, first, count, s, (char *)ws, ws_bytes);
 }
 
 // The w-plane lattice: planes j = 0 .. n_pairs (|w| = j dw), FP32 quadrature path.
-hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s) {
+hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s, void *ws, size_t ws_bytes) {
     BuildArgs A = common_args(c);
     const Plan &pl = c->plan;
     A.plane_off = pl.plane_off;
@@ -894,7 +1008,54 @@ hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s) {
     A.plane_dq = c->g.plane_dq;
     A.plane_dw = c->g.plane_dw;
     A.table2 = (float2 *)c->taps;
-    return run_build(c, A, 0, (int64_t)pl.n_pairs + 1, s);
+    return run_build(c, A, 0, (int64_t)pl.n_pairs + 1, s, (char *)ws, ws_bytes);
+}
+
+// Batch size of a build whose temporaries must fit `cap` bytes (0: none fits).
+int build_batch_in(const wsp_ctx *c, size_t cap) {
+    BuildArgs A = common_args(const_cast<wsp_ctx *>(c));
+    if (c->g.planes) A.plane_off = c->plan.plane_off;
+    const int64_t count = c->g.planes ? (int64_t)c->plan.n_pairs + 1 : c->plan.m;
+    int B = 0;
+    if (fitting_batch(c, A, count, cap, &B) != hipSuccess) return 0;
+    return B;
+}
+
+// ---- static build workspace ----------------------------------------------------------
+// For callers that cannot allocate device memory (graph capture, tight
+// serving loops): wsp_build_kernels_noalloc carves the build temporaries
+// from this array instead of hipMalloc.  Every device that loads the library
+// holds its own copy until the process ends.  Its device address is looked
+// up once per device (hipGetSymbolAddress, with that device current) when a
+// context is created there; host code uses only that address.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+hipError_t static_scratch_init(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // callers make `device` current first
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace wsp

@@ -185,6 +185,7 @@ struct wsp_ctx {
     int64_t built_upto = 0;         // visibilities built so far, in build order
     int64_t quad_panels = 0;
     int64_t quad_capped = 0;
+    void *static_scratch = nullptr; // device address of this device's static build workspace
     wsp::StageTimer timer;
 };
 
@@ -203,9 +204,15 @@ void free_sorted_plan(Plan &pl);
 
 hipError_t plane_setup(wsp_ctx *c, hipStream_t s);
 
-// build.hip
-hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s);
-hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s);
+// build.hip.  ws == nullptr: the build allocates its temporaries; otherwise
+// they are carved from [ws, ws + ws_bytes) and nothing is allocated.
+hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s, void *ws = nullptr,
+                        size_t ws_bytes = 0);
+hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s, void *ws = nullptr, size_t ws_bytes = 0);
+int build_batch_in(const wsp_ctx *c, size_t cap);  // batch size whose temporaries fit cap (0: none)
+// the static build workspace of the current device (see build.hip)
+hipError_t static_scratch_init(int device, void **ptr);
+size_t static_scratch_bytes();
 
 // api.cpp: stage timing around one launch (no-ops when timing is off)
 hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);

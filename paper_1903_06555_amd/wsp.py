@@ -48,7 +48,7 @@ KERNEL_MODES = {"exact": WSP_KERNELS_EXACT, "planes": WSP_KERNELS_PLANES}
 
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
             "wsp_set_dde", "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
-            "wsp_build_kernels", "wsp_build_kernels_part", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
+            "wsp_build_kernels", "wsp_build_kernels_part", "wsp_build_kernels_noalloc", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
             "wsp_degrid_pol", "wsp_grid_pol", "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
             "wsp_last_error")
 
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "wsp_bind_memory": (i32, [P, P, sz, P, sz, P, sz]),
         "wsp_build_kernels": (i32, [P, P]),
         "wsp_build_kernels_part": (i32, [P, i64, i64, P]),
+        "wsp_build_kernels_noalloc": (i32, [P, P]),
         "wsp_quad_stats": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "wsp_degrid": (i32, [P, P, P, P]),
         "wsp_grid": (i32, [P, P, P, P]),
@@ -211,6 +212,10 @@ def wsp_build_kernels(ctx, stream=None) -> int:
 
 def wsp_build_kernels_part(ctx, first: int, count: int, stream=None) -> int:
     return _check(load_library().wsp_build_kernels_part(ctx, first, count, _stream(stream)))
+
+
+def wsp_build_kernels_noalloc(ctx, stream=None) -> int:
+    return _check(load_library().wsp_build_kernels_noalloc(ctx, _stream(stream)))
 
 
 def wsp_quad_stats(ctx):
