@@ -94,3 +94,25 @@ def test_wide_field_large_w_converges_to_dft_as_support_grows():
     assert errs[0] < 5e-2
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 3 * e0, (errs, e0)
+
+
+def test_forward_at_and_adjoint_at_equal_the_fft_route():
+    """The cell-wise DFT evaluation equals the numpy FFT route, element by
+    element, with stacks, fold and weights, for sparse and dense images."""
+    uvw = syn.uniform_box_uvw(400, u_max=55.0, w_max=30.0, seed=31)
+    wts = syn.random_weights(400, seed=32)
+    op = operator.StackedOperator(GEOM, uvw, weights=wts, n_stacks=3, fold=True)
+    subset = np.random.default_rng(33).permutation(400)[:90]   # unsorted on purpose
+    for x in (syn.point_source_sky(GEOM.n, 25, "exp", 34), syn.random_image(GEOM.n, 35)):
+        y_fft = op.forward(x, subset=subset)
+        y_at = op.forward_at(x, subset)
+        assert np.count_nonzero(y_at) == subset.size
+        assert np.max(np.abs(y_at - y_fft)) <= 1e-12 * np.max(np.abs(y_fft))
+    y = np.zeros(400, dtype=np.complex128)
+    y[subset] = syn.random_vis(subset.size, seed=36)
+    x_fft = op.adjoint(y, subset=subset)
+    rng = np.random.default_rng(37)
+    rows = np.concatenate([[0, GEOM.n - 1, GEOM.n // 2], rng.integers(0, GEOM.n, 200)])
+    cols = np.concatenate([[0, GEOM.n - 1, GEOM.n // 2], rng.integers(0, GEOM.n, 200)])
+    x_at = op.adjoint_at(y, rows, cols, subset)
+    assert np.max(np.abs(x_at - x_fft[rows, cols])) <= 1e-12 * np.max(np.abs(x_fft))
