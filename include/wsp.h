@@ -72,7 +72,8 @@ typedef struct wsp_params {
     int32_t n_stacks;       /* K >= 1 w-stacks                                          */
     int32_t fold_conjugate; /* 1: fold w < 0 onto w > 0 by Eq. (8)                      */
     double quad_rel_tol;    /* quadrature tolerances (the paper's value is 1e-6, Sec. 4)*/
-    double quad_abs_tol;    /*   both relative to the visibility's kernel peak          */
+    double quad_abs_tol;    /*   both relative to the visibility's kernel peak; the
+                               smaller positive one bounds each tap's error estimate    */
     int32_t quad_max_panels;/* cap on quadrature panels per visibility (8..1024)       */
     int32_t max_support;    /* cap on J_p; larger supports give WSP_ESUPPORT            */
     int32_t precision;      /* WSP_FP32_FP64PHASE or WSP_FP64                           */
@@ -83,6 +84,12 @@ typedef struct wsp_params {
     double plane_dq;        /* w-plane mode: sample step in q (cells); 0 selects 1/64   */
     double plane_dw;        /* w-plane mode: plane step in |w| (wavelengths); 0: 1/16   */
     int32_t dde_support;    /* J_D: odd width of a per-visibility DDE kernel, 0 or 1 = none */
+    int32_t item_taps;      /* taps per tile work item before its last entry; 0: 2^19 (a
+                               tuning and test knob: small values split tiles over items) */
+    int32_t band_rows;      /* exact mode: tile rows per band of the tap layout, 8 or 16;
+                               0 chooses from the plan (16 when the mean taps per
+                               (visibility, tile) overlap is below 160). Results do
+                               not depend on it beyond rounding order               */
 } wsp_params;
 
 /* Direction-dependent effects (Sec. 5.2, Eq. (11)).  With dde_support = J_D
@@ -127,8 +134,9 @@ typedef struct wsp_ctx wsp_ctx;
  * tolerance 1e-3 and 100 iterations, device 0.  n and fov_rad are left 0. */
 void wsp_default_params(wsp_params *p);
 
-/* Validate *p and create a context on p->device.  Builds the batched 2-D FFT
- * plan of the K stacks (G x G, G = alpha N) without allocating its work area.
+/* Validate *p and create a context on p->device.  Makes the batched 1-D FFT
+ * plans of length G = alpha N that carry F and F^dagger of the K stacks as
+ * passes along v and u (their work area lives in the caller's scratch).
  * Errors: WSP_EINVAL (parameters), WSP_EHIP. */
 wsp_status wsp_create(const wsp_params *p, wsp_ctx **out);
 
@@ -168,7 +176,41 @@ wsp_status wsp_get_stacks(const wsp_ctx *ctx, int32_t *labels, double *centres,
  * fold flags (host uint8 [M] or NULL).  Errors: WSP_ESTATE. */
 wsp_status wsp_get_support(const wsp_ctx *ctx, int32_t *jp, uint8_t *folded);
 
-/* Exact byte sizes of the caller-owned buffers after wsp_set_uvw:
+/* Statistics of the plan made by wsp_set_uvw / wsp_set_stacks (Sec. 3.1-3.3:
+ * the supports of Eq. (5), the w-stacks of Algorithm 1, the tile work lists)
+ * and the device memory the library holds itself. */
+typedef struct wsp_plan_info {
+    int64_t visibilities;     /* M                                                       */
+    int64_t taps;             /* sum_p J_p^2                                             */
+    int64_t entries;          /* (visibility, 64 x 64 grid tile) overlaps                */
+    int64_t runs;             /* (entry, band of band_rows tile rows) parts; 0 in w-plane mode */
+    int64_t items;            /* tile work items                                          */
+    int64_t tiles;            /* distinct (stack, tile) pairs that hold taps             */
+    int64_t split_tiles;      /* tiles whose entries are split over several items       */
+    int64_t touched_cells;    /* distinct (stack, grid cell) pairs some tap falls on     */
+    int64_t plan_bytes;       /* device bytes the library holds for the context now (its
+                                 plan, the DDE kernels, the stack centres), counted
+                                 allocation by allocation                              */
+    int64_t plan_peak_bytes;  /* the same at its peak during the last wsp_set_uvw /
+                                 wsp_set_stacks (planning temporaries included)        */
+    int64_t build_temp_bytes; /* upper bound on the device bytes wsp_build_kernels
+                                 allocates beyond plan_bytes and frees before it returns
+                                 (admission can add it before building)                */
+    int64_t last_build_temp_bytes; /* the same, measured during the last build (0 before
+                                 one; wsp_build_kernels_noalloc allocates nothing)     */
+    int32_t max_support;      /* largest J_p                                              */
+    int32_t kmeans_iterations;/* Algorithm 1 iterations (0 after wsp_set_stacks)          */
+    int32_t band_rows;        /* tile rows per band of the exact tap layout (0 in w-plane mode) */
+    int32_t reserved;         /* 0                                                        */
+} wsp_plan_info;
+
+/* Fill *info.  touched_cells is counted on the device (synchronises it).
+ * Errors: WSP_ESTATE (no plan), WSP_EINVAL, WSP_EHIP. */
+wsp_status wsp_plan_stats(wsp_ctx *ctx, wsp_plan_info *info);
+
+/* Exact byte sizes of the caller-owned buffers after wsp_set_uvw (the
+ * memory the library allocates itself is reported by wsp_plan_stats:
+ * plan_bytes held, plus up to build_temp_bytes during a build):
  * kernel taps (sum_p J_p^2 complex values; in w-plane mode the w-plane
  * lattice instead, 16 bytes per sample pair), the K Fourier grids (K G^2
  * complex values) and scratch (FFT work area, M complex values, one complex
@@ -220,7 +262,8 @@ wsp_status wsp_build_kernels_part(wsp_ctx *ctx, int64_t first, int64_t count, vo
 wsp_status wsp_build_kernels_noalloc(wsp_ctx *ctx, void *stream);
 
 /* Quadrature statistics of the last build: total panels, and visibilities
- * whose panel cap was reached.  Errors: WSP_ESTATE. */
+ * whose quadrature could not meet the tolerance (the panel cap was reached,
+ * or a panel over the tolerance was too narrow to split).  Errors: WSP_ESTATE. */
 wsp_status wsp_quad_stats(const wsp_ctx *ctx, int64_t *panels, int64_t *capped);
 
 /* y = Phi x (Eq. (2)-(5)): per stack, taper and w-bar chirp (S~_k), zero pad
@@ -236,6 +279,18 @@ wsp_status wsp_degrid(wsp_ctx *ctx, const void *image, void *vis, void *stream);
  * stacks.  vis: device complex [M] (caller order); image: device real [N][N],
  * overwritten.  Asynchronous on the stream.  Errors as wsp_degrid. */
 wsp_status wsp_grid(wsp_ctx *ctx, const void *vis, void *image, void *stream);
+
+/* wsp_degrid / wsp_grid on the caller's (grids, scratch) pair instead of
+ * the bound one (each at least its wsp_footprint size, 256-byte aligned,
+ * device memory the caller owns).  The taps stay the bound ones.  Several
+ * requests on one context can then run at once on different streams, each
+ * with its own pair (the serving loop's slots).  Host calls on one context
+ * must still not overlap.  Errors: as wsp_degrid, WSP_ENOMEM_BINDING (a
+ * buffer NULL or too small), WSP_EINVAL (misaligned). */
+wsp_status wsp_degrid_ws(wsp_ctx *ctx, const void *image, void *vis, void *grids, size_t grid_bytes,
+                         void *scratch, size_t scratch_bytes, void *stream);
+wsp_status wsp_grid_ws(wsp_ctx *ctx, const void *vis, void *image, void *grids, size_t grid_bytes,
+                       void *scratch, size_t scratch_bytes, void *stream);
 
 /* Linear polarisation (Sec. 3.3, Eq. (9)).  Stokes Q and U are real images,
  * P = Q + iU and y_P = y_Q + i y_U.  Folding reflects each real Stokes image's

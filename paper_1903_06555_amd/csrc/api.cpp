@@ -10,6 +10,10 @@
 
 using namespace wsp;
 
+namespace wsp {
+thread_local AllocTrack *g_track = nullptr;
+}  // namespace wsp
+
 namespace {
 
 thread_local std::string g_err;
@@ -42,12 +46,12 @@ double bessel_i0(double x) {
 }
 
 void free_caller(Plan &pl) {
-    hipFree(pl.u);
-    hipFree(pl.v);
-    hipFree(pl.w);
-    hipFree(pl.wt_in);
-    hipFree(pl.flag);
-    hipFree(pl.label);
+    dfree(pl.u);
+    dfree(pl.v);
+    dfree(pl.w);
+    dfree(pl.wt_in);
+    dfree(pl.flag);
+    dfree(pl.label);
     pl.u = pl.v = pl.w = pl.wt_in = nullptr;
     pl.flag = nullptr;
     pl.label = nullptr;
@@ -113,7 +117,16 @@ hipfftResult make_row_plans(wsp_ctx *c) {
     return HIPFFT_SUCCESS;
 }
 
+wsp_status finish_plan_inner(wsp_ctx *c, hipStream_t s);
+
+// Plan, and record the planning call's device-memory peak.
 wsp_status finish_plan(wsp_ctx *c, hipStream_t s) {
+    const wsp_status st = finish_plan_inner(c, s);
+    c->plan_peak = c->track.peak;
+    return st;
+}
+
+wsp_status finish_plan_inner(wsp_ctx *c, hipStream_t s) {
     int support_err = 0;
     hipError_t e = make_plan(c, c->plan_centres, s, &support_err);
     if (e != hipSuccess) return hip_fail(e, "planning");
@@ -158,6 +171,10 @@ namespace {
 // the half-size transform buffer: K x N rows of G cells
 size_t half_bytes(const wsp_ctx *c) {
     return (size_t)c->g.n_stacks * c->g.n * c->g.G * cplx_bytes(c);
+}
+// degrid partial sums: one per run (exact kernels) or per tile entry (w-plane kernels)
+size_t n_partials(const wsp_ctx *c) {
+    return (size_t)(c->g.planes ? c->plan.n_entries : c->plan.n_runs);
 }
 }  // namespace
 
@@ -273,6 +290,10 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
         return fail(WSP_EINVAL, "dde_support must be 0, 1 or odd in [3, 15]");
     if (p.dde_support > 1 && p.kernel_mode == WSP_KERNELS_PLANES)
         return fail(WSP_EINVAL, "DDE convolution needs stored (exact) kernels");
+    if (p.item_taps < 0 || p.item_taps > (1 << 24))
+        return fail(WSP_EINVAL, "item_taps must be in [0, 2^24] (0 = default)");
+    if (p.band_rows != 0 && p.band_rows != 8 && p.band_rows != 16)
+        return fail(WSP_EINVAL, "band_rows must be 0, 8 or 16");
     if (!(p.plane_dq >= 0.0) || !(p.plane_dw >= 0.0) || !std::isfinite(p.plane_dq) ||
         !std::isfinite(p.plane_dw) || p.plane_dq > 1.0)
         return fail(WSP_EINVAL, "plane_dq must be in [0, 1] and plane_dw >= 0 (0 = default)");
@@ -302,6 +323,8 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     g.plane_inv_dq = 1.0 / g.plane_dq;
     g.plane_inv_dw = 1.0 / g.plane_dw;
     g.dde_h = p.dde_support > 1 ? (p.dde_support - 1) / 2 : 0;
+    g.item_taps = p.item_taps > 0 ? (int64_t)p.item_taps : kItemTaps;
+    g.band_rows_param = p.band_rows;
     double xr = 2.0 * M_PI * g.a * g.r_max;
     double ymax = std::fmax(0.25 * g.beta * g.beta, std::fabs(0.25 * (g.beta * g.beta - xr * xr)));
     int terms = (int)std::ceil(2.0 * std::sqrt(ymax)) + 30;
@@ -322,6 +345,7 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     wsp_ctx *c = new (std::nothrow) wsp_ctx();
     if (!c) return fail(WSP_EHIP, "out of host memory");
     c->static_scratch = static_ws;
+    TrackScope track(&c->track);
     c->p = p;
     c->g = g;
     c->device = p.device;
@@ -354,7 +378,7 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
         c->g.rows_lo = g.G;
         c->g.rows_hi = 0;
     }
-    e = hipMalloc(&c->plan_centres, sizeof(double) * g.n_stacks);
+    e = dmalloc(&c->plan_centres, sizeof(double) * g.n_stacks);
     if (e != hipSuccess) {
         hipfftDestroy(c->fft_v);
         hipfftDestroy(c->fft_u);
@@ -370,30 +394,32 @@ wsp_status wsp_set_uvw(wsp_ctx *c, const double *uvw, int64_t m, const double *w
     if (!c || !uvw) return fail(WSP_EINVAL, "null argument");
     if (m <= 0 || m > 0x7FFFFFF0LL) return fail(WSP_EINVAL, "m must be in [1, 2^31)");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    TrackScope track(&c->track);
     hipStream_t s = as_stream(stream);
     Plan &pl = c->plan;
     free_sorted_plan(pl);
     free_caller(pl);
-    hipFree(c->dde_u);
-    hipFree(c->dde_v);
+    dfree(c->dde_u);
+    dfree(c->dde_v);
     c->dde_u = c->dde_v = nullptr;
     c->dde_set = false;
     c->planned = c->bound = c->built = false;
+    c->track.peak = c->track.cur;  // planning peak measured from here (finish_plan records it)
     pl.m = m;
-    HIP_OR_FAIL(hipMalloc(&pl.u, sizeof(double) * m), "hipMalloc");
-    HIP_OR_FAIL(hipMalloc(&pl.v, sizeof(double) * m), "hipMalloc");
-    HIP_OR_FAIL(hipMalloc(&pl.w, sizeof(double) * m), "hipMalloc");
-    HIP_OR_FAIL(hipMalloc(&pl.wt_in, sizeof(double) * m), "hipMalloc");
-    HIP_OR_FAIL(hipMalloc(&pl.flag, m), "hipMalloc");
-    HIP_OR_FAIL(hipMalloc(&pl.label, sizeof(int32_t) * m), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&pl.u, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&pl.v, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&pl.w, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&pl.wt_in, sizeof(double) * m), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&pl.flag, m), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&pl.label, sizeof(int32_t) * m), "hipMalloc");
     int *d_bad = nullptr;
-    HIP_OR_FAIL(hipMalloc(&d_bad, sizeof(int)), "hipMalloc");
+    HIP_OR_FAIL(dmalloc(&d_bad, sizeof(int)), "hipMalloc");
     hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(int), s);
     if (e == hipSuccess) e = launch_fold(uvw, weights, m, c->p.fold_conjugate, pl, d_bad, s);
     int bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(d_bad);
+    dfree(d_bad);
     if (e != hipSuccess) return hip_fail(e, "fold");
     if (bad) return fail(WSP_EINVAL, "non-finite uvw or weight");
 
@@ -441,6 +467,8 @@ wsp_status wsp_set_stacks(wsp_ctx *c, const int32_t *labels, const double *centr
     for (int q = 0; q < K; ++q)
         if (!std::isfinite(centres[q])) return fail(WSP_EINVAL, "non-finite centre");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    TrackScope track(&c->track);
+    c->track.peak = c->track.cur;
     hipStream_t s = as_stream(stream);
     HIP_OR_FAIL(hipMemcpyAsync(c->plan.label, labels, sizeof(int32_t) * c->plan.m,
                                hipMemcpyHostToDevice, s), "labels");
@@ -456,9 +484,10 @@ wsp_status wsp_set_dde(wsp_ctx *c, const void *d_u, const void *d_v, void *strea
     if (!c->plan.u) return fail(WSP_ESTATE, "wsp_set_uvw first");
     if (c->g.dde_h == 0) return fail(WSP_ESTATE, "dde_support is not set (>= 3)");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    TrackScope track(&c->track);
     const size_t bytes = (size_t)c->plan.m * (size_t)(2 * c->g.dde_h + 1) * cplx_bytes(c);
-    if (!c->dde_u) HIP_OR_FAIL(hipMalloc(&c->dde_u, bytes), "hipMalloc");
-    if (!c->dde_v) HIP_OR_FAIL(hipMalloc(&c->dde_v, bytes), "hipMalloc");
+    if (!c->dde_u) HIP_OR_FAIL(dmalloc(&c->dde_u, bytes), "hipMalloc");
+    if (!c->dde_v) HIP_OR_FAIL(dmalloc(&c->dde_v, bytes), "hipMalloc");
     hipStream_t s = as_stream(stream);
     HIP_OR_FAIL(hipMemcpyAsync(c->dde_u, d_u, bytes, hipMemcpyDeviceToDevice, s), "DDE copy");
     HIP_OR_FAIL(hipMemcpyAsync(c->dde_v, d_v, bytes, hipMemcpyDeviceToDevice, s), "DDE copy");
@@ -497,6 +526,35 @@ wsp_status wsp_get_support(const wsp_ctx *c, int32_t *jp, uint8_t *folded) {
     return WSP_OK;
 }
 
+wsp_status wsp_plan_stats(wsp_ctx *c, wsp_plan_info *info) {
+    if (!c || !info) return fail(WSP_EINVAL, "null argument");
+    if (!c->planned) return fail(WSP_ESTATE, "wsp_set_uvw first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    const size_t resident = c->track.cur;  // before the transient bitmap of the cell count
+    TrackScope track(&c->track);
+    const Plan &pl = c->plan;
+    std::memset(info, 0, sizeof(*info));
+    info->visibilities = pl.m;
+    info->taps = pl.total_taps;
+    info->entries = pl.n_entries;
+    info->runs = pl.n_runs;
+    info->items = pl.n_items;
+    info->tiles = pl.n_items - pl.n_multi + pl.n_mtiles;
+    info->split_tiles = pl.n_mtiles;
+    int64_t cells = 0;
+    HIP_OR_FAIL(count_touched_cells(c, &cells), "touched cells");
+    info->touched_cells = cells;
+    info->plan_bytes = (int64_t)resident;
+    info->plan_peak_bytes = (int64_t)c->plan_peak;
+    info->build_temp_bytes = (int64_t)build_temp_bytes(c);
+    info->last_build_temp_bytes = (int64_t)c->build_peak;
+    info->max_support = pl.max_jp;
+    info->kmeans_iterations = c->iterations;
+    info->band_rows = c->g.planes ? 0 : pl.tile_band_rows;
+    info->reserved = 0;
+    return WSP_OK;
+}
+
 wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_bytes,
                          size_t *scratch_bytes) {
     if (!c) return fail(WSP_EINVAL, "null argument");
@@ -507,10 +565,59 @@ wsp_status wsp_footprint(const wsp_ctx *c, size_t *kernel_bytes, size_t *grid_by
     if (grid_bytes) *grid_bytes = (size_t)c->g.G * c->g.G * c->g.n_stacks * cb;
     if (scratch_bytes)
         *scratch_bytes = align256(c->fft_work) + align256(half_bytes(c)) + align256((size_t)c->plan.m * cb) +
-                         align256((size_t)c->plan.n_entries * cb) +
-                         (size_t)c->plan.n_multi * kTile * kTile * cb;
+                         align256(n_partials(c) * cb) + (size_t)c->plan.n_multi * kTile * kTile * cb;
     return WSP_OK;
 }
+
+}  // extern "C"
+
+namespace {
+// Point the operator at a (grids, scratch) pair: the scratch's parts and the
+// FFT plans' work area.
+bool use_workspace(wsp_ctx *c, void *grids, void *scratch) {
+    if (c->fft_work > 0) {
+        bool ok = hipfftSetWorkArea(c->fft_v, scratch) == HIPFFT_SUCCESS &&
+                  hipfftSetWorkArea(c->fft_u, scratch) == HIPFFT_SUCCESS;
+        if (c->fft_ulo_made) ok = ok && hipfftSetWorkArea(c->fft_ulo, scratch) == HIPFFT_SUCCESS;
+        if (c->fft_ujoin_made) ok = ok && hipfftSetWorkArea(c->fft_ujoin, scratch) == HIPFFT_SUCCESS;
+        if (c->fft_uhi_made) ok = ok && hipfftSetWorkArea(c->fft_uhi, scratch) == HIPFFT_SUCCESS;
+        if (!ok) return false;
+    }
+    c->scratch_half = (char *)scratch + align256(c->fft_work);
+    c->scratch_yw = (char *)c->scratch_half + align256(half_bytes(c));
+    c->scratch_dpart = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
+    c->scratch_part = (char *)c->scratch_dpart + align256(n_partials(c) * cplx_bytes(c));
+    c->grids = grids;
+    c->scratch = scratch;
+    return true;
+}
+
+// Run one degrid / grid call on another (grids, scratch) pair, then point
+// the operator back at the bound pair.  Kernels and FFTs take their buffer
+// addresses when they are launched, so the swap does not affect launches
+// already on a stream.
+template <typename F>
+wsp_status with_workspace(wsp_ctx *c, void *grids, size_t grid_bytes, void *scratch, size_t scratch_bytes,
+                          const char *what, F &&run) {
+    size_t kb = 0, gb = 0, sb = 0;
+    wsp_footprint(c, &kb, &gb, &sb);
+    if (!grids || (sb > 0 && !scratch)) return fail(WSP_ENOMEM_BINDING, "null workspace");
+    if (grid_bytes < gb || scratch_bytes < sb) return fail(WSP_ENOMEM_BINDING, "workspace smaller than wsp_footprint");
+    if (((uintptr_t)grids | (uintptr_t)scratch) & 255u) return fail(WSP_EINVAL, "buffers must be 256-byte aligned");
+    void *g0 = c->grids, *s0 = c->scratch;
+    if (!use_workspace(c, grids, scratch)) {
+        use_workspace(c, g0, s0);
+        return fail(WSP_EHIP, "hipfftSetWorkArea failed");
+    }
+    const hipError_t e = run();
+    const bool back = use_workspace(c, g0, s0);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (!back) return fail(WSP_EHIP, "hipfftSetWorkArea failed");
+    return WSP_OK;
+}
+}  // namespace
+
+extern "C" {
 
 wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void *grids,
                            size_t grid_bytes, void *scratch, size_t scratch_bytes) {
@@ -524,24 +631,10 @@ wsp_status wsp_bind_memory(wsp_ctx *c, void *kernels, size_t kernel_bytes, void 
         return fail(WSP_ENOMEM_BINDING, "buffer smaller than wsp_footprint");
     if (((uintptr_t)kernels | (uintptr_t)grids | (uintptr_t)scratch) & 255u)
         return fail(WSP_EINVAL, "buffers must be 256-byte aligned");
-    if (c->fft_work > 0) {
-        bool ok = hipfftSetWorkArea(c->fft_v, scratch) == HIPFFT_SUCCESS &&
-                  hipfftSetWorkArea(c->fft_u, scratch) == HIPFFT_SUCCESS;
-        if (c->fft_ulo_made) ok = ok && hipfftSetWorkArea(c->fft_ulo, scratch) == HIPFFT_SUCCESS;
-        if (c->fft_ujoin_made) ok = ok && hipfftSetWorkArea(c->fft_ujoin, scratch) == HIPFFT_SUCCESS;
-        if (c->fft_uhi_made) ok = ok && hipfftSetWorkArea(c->fft_uhi, scratch) == HIPFFT_SUCCESS;
-        if (!ok) return fail(WSP_EHIP, "hipfftSetWorkArea failed");
-    }
-    c->scratch_half = (char *)scratch + align256(c->fft_work);
-    c->scratch_yw = (char *)c->scratch_half + align256(half_bytes(c));
-    c->scratch_dpart = (char *)c->scratch_yw + align256((size_t)c->plan.m * cplx_bytes(c));
-    c->scratch_part =
-        (char *)c->scratch_dpart + align256((size_t)c->plan.n_entries * cplx_bytes(c));
+    if (!use_workspace(c, grids, scratch)) return fail(WSP_EHIP, "hipfftSetWorkArea failed");
     c->taps = kernels;
     c->taps_bytes = kernel_bytes;
-    c->grids = grids;
     c->grid_bytes = grid_bytes;
-    c->scratch = scratch;
     c->scratch_bytes = scratch_bytes;
     c->bound = true;
     c->built = false;
@@ -559,6 +652,18 @@ wsp_status build_part(wsp_ctx *c, int64_t first, int64_t count, void *stream, vo
     if (c->g.dde_h > 0 && !c->dde_set) return fail(WSP_ESTATE, "wsp_set_dde first");
     if (count <= 0 || first + count > c->plan.m) return fail(WSP_EINVAL, "bad visibility range");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    TrackScope track(&c->track);
+    const size_t resident = c->track.cur;
+    c->track.peak = resident;
+    struct PeakRecord {  // the build's transient peak, on every return path
+        wsp_ctx *c;
+        size_t base;
+        ~PeakRecord() {
+            const size_t over = c->track.peak - base;
+            if (over > c->build_peak) c->build_peak = over;
+        }
+    } record{c, resident};
+    if (first == 0) c->build_peak = 0;
     hipStream_t s = as_stream(stream);
     if (c->g.planes) {
         // the lattice serves every visibility: built by the first part
@@ -580,7 +685,8 @@ wsp_status build_part(wsp_ctx *c, int64_t first, int64_t count, void *stream, vo
     c->built_upto = first + count;
     c->built = c->built_upto == c->plan.m;
     if (st[1] > 0) {
-        g_err = std::to_string(st[1]) + " visibilities reached quad_max_panels";
+        g_err = std::to_string(st[1]) + " visibilities did not meet the quadrature tolerance "
+                "(quad_max_panels reached, or a panel too narrow to split)";
         return WSP_WARN_QUAD_MAXEVAL;
     }
     return WSP_OK;
@@ -636,6 +742,24 @@ wsp_status wsp_grid(wsp_ctx *c, const void *vis, void *image, void *stream) {
     return WSP_OK;
 }
 
+wsp_status wsp_degrid_ws(wsp_ctx *c, const void *image, void *vis, void *grids, size_t grid_bytes,
+                         void *scratch, size_t scratch_bytes, void *stream) {
+    if (!c || !image || !vis) return fail(WSP_EINVAL, "null argument");
+    if (!c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    return with_workspace(c, grids, grid_bytes, scratch, scratch_bytes, "degrid",
+                          [&]() { return run_degrid(c, image, vis, as_stream(stream)); });
+}
+
+wsp_status wsp_grid_ws(wsp_ctx *c, const void *vis, void *image, void *grids, size_t grid_bytes, void *scratch,
+                       size_t scratch_bytes, void *stream) {
+    if (!c || !image || !vis) return fail(WSP_EINVAL, "null argument");
+    if (!c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
+    HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    return with_workspace(c, grids, grid_bytes, scratch, scratch_bytes, "grid",
+                          [&]() { return run_grid(c, vis, image, as_stream(stream)); });
+}
+
 wsp_status wsp_degrid_pol(wsp_ctx *c, const void *q_image, const void *u_image, void *vis,
                           void *stream) {
     if (!c || !q_image || !u_image || !vis) return fail(WSP_EINVAL, "null argument");
@@ -665,49 +789,27 @@ wsp_status wsp_kernel_values(wsp_ctx *c, int64_t p, void *out, int32_t *jp, int3
     if (out && !c->built) return fail(WSP_ESTATE, "wsp_build_kernels first");
     if (p < 0 || p >= c->plan.m) return fail(WSP_EINVAL, "visibility index out of range");
     HIP_OR_FAIL(hipSetDevice(c->device), "hipSetDevice");
+    TrackScope track(&c->track);
     HIP_OR_FAIL(hipDeviceSynchronize(), "sync");
-    const int64_t m = c->plan.m;
-    std::vector<int32_t> perm(m);
-    HIP_OR_FAIL(hipMemcpy(perm.data(), c->plan.perm, sizeof(int32_t) * m, hipMemcpyDeviceToHost), "perm");
     int64_t sidx = -1;
-    for (int64_t i = 0; i < m; ++i)
-        if (perm[i] == p) {
-            sidx = i;
-            break;
-        }
+    HIP_OR_FAIL(find_sorted_index(c, p, &sidx), "permutation lookup");
     if (sidx < 0) return fail(WSP_EHIP, "permutation lookup failed");
     int32_t j = 0;
-    int64_t off = 0;
     double uu = 0, vv = 0;
     HIP_OR_FAIL(hipMemcpy(&j, c->plan.jp + sidx, sizeof(int32_t), hipMemcpyDeviceToHost), "jp");
-    HIP_OR_FAIL(hipMemcpy(&off, c->plan.tap_off + sidx, sizeof(int64_t), hipMemcpyDeviceToHost), "off");
     HIP_OR_FAIL(hipMemcpy(&uu, c->plan.u + p, sizeof(double), hipMemcpyDeviceToHost), "u");
     HIP_OR_FAIL(hipMemcpy(&vv, c->plan.v + p, sizeof(double), hipMemcpyDeviceToHost), "v");
     if (jp) *jp = j;
     if (u0) *u0 = (int32_t)((int64_t)std::floor(uu * c->g.inv_du) - j / 2 + 1);
     if (v0) *v0 = (int32_t)((int64_t)std::floor(vv * c->g.inv_du) - j / 2 + 1);
-    if (out && c->g.planes) {
+    if (out) {
+        const size_t bytes = (size_t)j * j * (c->g.planes ? sizeof(float) * 2 : cplx_bytes(c));
         void *d = nullptr;
-        const size_t bytes = (size_t)j * j * sizeof(float) * 2;
-        HIP_OR_FAIL(hipMalloc(&d, bytes), "hipMalloc");
-        hipError_t e = run_plane_taps(c, sidx, d, nullptr);
+        HIP_OR_FAIL(dmalloc(&d, bytes), "hipMalloc");
+        hipError_t e = c->g.planes ? run_plane_taps(c, sidx, d, nullptr) : run_exact_taps(c, sidx, d, nullptr);
         if (e == hipSuccess) e = hipMemcpy(out, d, bytes, hipMemcpyDeviceToHost);
-        hipFree(d);
-        if (e != hipSuccess) return hip_fail(e, "w-plane taps");
-    } else if (out) {
-        // copy the visibility's block and undo the tile grouping (row-major out)
-        const size_t cb = cplx_bytes(c);
-        int32_t uw = 0, vw = 0;
-        HIP_OR_FAIL(hipMemcpy(&uw, c->plan.u0w + sidx, sizeof(int32_t), hipMemcpyDeviceToHost), "u0w");
-        HIP_OR_FAIL(hipMemcpy(&vw, c->plan.v0w + sidx, sizeof(int32_t), hipMemcpyDeviceToHost), "v0w");
-        std::vector<char> blk((size_t)j * j * cb);
-        HIP_OR_FAIL(hipMemcpy(blk.data(), (const char *)c->taps + off * cb, blk.size(),
-                              hipMemcpyDeviceToHost), "taps");
-        char *o = (char *)out;
-        for (int row = 0; row < j; ++row)
-            for (int col = 0; col < j; ++col)
-                std::memcpy(o + ((size_t)row * j + col) * cb,
-                            blk.data() + blocked_tap_index(row, col, j, uw, vw) * cb, cb);
+        dfree(d);
+        if (e != hipSuccess) return hip_fail(e, "kernel taps");
     }
     return WSP_OK;
 }
@@ -738,13 +840,14 @@ wsp_status wsp_stage_times(wsp_ctx *c, double *ms, int64_t *counts) {
 void wsp_destroy(wsp_ctx *c) {
     if (!c) return;
     hipSetDevice(c->device);
+    TrackScope track(&c->track);
     drain_timer(c);
     for (hipEvent_t ev : c->timer.pool) hipEventDestroy(ev);
     free_sorted_plan(c->plan);
     free_caller(c->plan);
-    hipFree(c->dde_u);
-    hipFree(c->dde_v);
-    hipFree(c->plan_centres);
+    dfree(c->dde_u);
+    dfree(c->dde_v);
+    dfree(c->plan_centres);
     if (c->fft_v_made) hipfftDestroy(c->fft_v);
     if (c->fft_u_made) hipfftDestroy(c->fft_u);
     destroy_row_plans(c);

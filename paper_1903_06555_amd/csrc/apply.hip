@@ -307,11 +307,15 @@ __device__ __forceinline__ int xcd_item_part(int b, int n, int kH, int *part) {
 
 // First cell of a (stack, tile) key in the grids.
 template <typename C>
+__device__ __forceinline__ C *tile_origin(C *grids, uint32_t key, int tile_bits, int G) {
+    const int tmask = (1 << tile_bits) - 1;
+    const int tx = key & tmask, ty = (key >> tile_bits) & tmask;
+    const int k = key >> (2 * tile_bits);
+    return grids + (int64_t)k * G * G + (int64_t)ty * kTile * G + (int64_t)tx * kTile;
+}
+template <typename C>
 __device__ __forceinline__ C *tile_origin(C *grids, uint32_t key, const TileArgs &t) {
-    const int tmask = (1 << t.tile_bits) - 1;
-    const int tx = key & tmask, ty = (key >> t.tile_bits) & tmask;
-    const int k = key >> (2 * t.tile_bits);
-    return grids + (int64_t)k * t.G * t.G + (int64_t)ty * kTile * t.G + (int64_t)tx * kTile;
+    return tile_origin(grids, key, t.tile_bits, t.G);
 }
 
 constexpr int kWaves = 8;             // wavefronts per block of the tile kernels
@@ -936,6 +940,266 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
     for (int r = 0; r < kBand; ++r) dst[(int64_t)(band0 + r) * ld + lane] = tile[(lrow0 + r) * kTile + lane];
 }
 
+// ---- exact kernels on the band-major tap layout ------------------------------
+// A unit is one band (kBR rows, 8 or 16) of one work item's 64 x 64 tile; its
+// runs (the parts of the item's entries in the band) and their taps are
+// contiguous in the tap array.  One wavefront serves one unit and holds the
+// unit's band of the tile in LDS; the wavefronts of a block are independent
+// (no block barriers), so a block only groups them for the LDS allocation.
+struct RunArgs {
+    const int4 *runrec;
+    const int32_t *unit_run0;
+    const int64_t *unit_tap0;
+    const uint32_t *item_key;
+    const uint8_t *item_sole;
+    const int32_t *item_slot;
+    void *partial;
+    int64_t n_units;
+    int tile_bits;
+    int G;
+};
+
+constexpr int kRunWaves = 4;   // wavefronts (units) per block
+constexpr int kRunChunk = 64;  // run records a grid wavefront stages in LDS at a time
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// number of set bits of m in lanes <= lane
+__device__ __forceinline__ int bits_upto(uint64_t m, int lane) {
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    return below + (int)((m >> lane) & 1ull);
+}
+
+// GC_k, W_k (degrid) on runs: a wavefront stages its unit's band of the FFT
+// grid, then groups of kG lanes take one run each (64 / kG consecutive runs
+// per pass), multiply its taps by the staged grid values and reduce; the
+// run's partial sum goes to dpart at the run's generation index (runs of a
+// visibility are consecutive there), summed per visibility by
+// k_degrid_reduce_runs.  kG follows the mean run length (short runs: narrow
+// groups, so a pass covers more runs and keeps more loads in flight); the
+// next pass's run records are loaded before this pass's taps are consumed.
+template <bool kFP64, int kG, int kBR>
+__global__ __launch_bounds__(64 * kRunWaves) void k_degrid_runs(const typename Types<kFP64>::C *__restrict__ taps,
+                                                                const typename Types<kFP64>::C *__restrict__ grids,
+                                                                typename Types<kFP64>::C *dpart, RunArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    constexpr int kPer = 64 / kG;               // runs per pass
+    constexpr int kU = kG >= 64 ? 8 : 512 / (kG * 8) > 8 ? 8 : 512 / (kG * 8);  // load slots per lane
+    __shared__ C s_band[kRunWaves][kBR * kTile];
+    const int wid = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
+    if (u >= a.n_units) return;  // uniform over the wavefront
+    const int r_beg = a.unit_run0[u], r_end = a.unit_run0[u + 1];
+    if (r_beg >= r_end) return;
+    constexpr int kNB = kTile / kBR;
+    const int item = (int)(u / kNB), band = (int)(u % kNB);
+    C *sb = s_band[wid];
+    {
+        const C *src = tile_origin(grids, a.item_key[item], a.tile_bits, a.G) + (int64_t)band * kBR * a.G;
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
+    }
+    wave_fence();
+    const C *tp = taps + a.unit_tap0[u];
+    const int grp = lane / kG, gl = lane % kG;
+    int4 nxt = a.runrec[r_beg + grp < r_end ? r_beg + grp : r_beg];
+    for (int rb = r_beg; rb < r_end; rb += kPer) {
+        const int r = rb + grp;
+        const bool valid = r < r_end;
+        const int4 rec = nxt;
+        if (rb + kPer < r_end) nxt = a.runrec[rb + kPer + grp < r_end ? rb + kPer + grp : rb + kPer];
+        const int nc = (rec.y >> 16) & 255, nrows = (rec.y >> 24) & 255, cell0 = rec.y & 0xFFFF;
+        const int ntap = valid ? nrows * nc : 0;
+        const float inv_nc = recip_nc(nc);
+        const C *rp = tp + rec.x;
+        R ar = 0, ai = 0;
+        for (int k0 = 0; __any(k0 < ntap); k0 += kG * kU) {
+            C K[kU];
+            int li[kU];
+#pragma unroll
+            for (int sl = 0; sl < kU; ++sl) {
+                K[sl].x = 0;
+                K[sl].y = 0;
+                li[sl] = cell0;
+                const int k = k0 + kG * sl + gl;
+                const bool ok = k < ntap;
+                if (__any(ok)) {
+                    const int kk = ok ? k : 0;
+                    const int row = sub_row(kk, inv_nc);
+                    li[sl] = sub_cell(cell0, kk, row, nc);
+                    if (ok) K[sl] = load_tap(rp + k);
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < kU; ++sl) {
+                const C z = sb[li[sl]];
+                ar += K[sl].x * z.x - K[sl].y * z.y;
+                ai += K[sl].x * z.y + K[sl].y * z.x;
+            }
+        }
+#pragma unroll
+        for (int o = kG / 2; o > 0; o >>= 1) {
+            ar += __shfl_xor(ar, o, 64);
+            ai += __shfl_xor(ai, o, 64);
+        }
+        if (gl == 0 && valid) {
+            C o;
+            o.x = ar;
+            o.y = ai;
+            dpart[rec.w] = o;
+        }
+    }
+}
+
+// y[perm[p]] = W_p (conj) sum of visibility p's run partials, in generation
+// order (its entries in turn, each entry's bands in turn): deterministic.
+template <bool kFP64>
+__global__ void k_degrid_reduce_runs(const typename Types<kFP64>::C *__restrict__ dpart,
+                                     const int64_t *__restrict__ ent_off, const int32_t *__restrict__ run_first,
+                                     typename Types<kFP64>::C *vis, ApplyArgs a, int add_i) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.m) return;
+    R ar = 0, ai = 0;
+    const int g1 = run_first[ent_off[p + 1]];
+    for (int g = run_first[ent_off[p]]; g < g1; ++g) {
+        const C v = dpart[g];
+        ar += v.x;
+        ai += v.y;
+    }
+    const R w = (R)a.wt[p];
+    C y;
+    y.x = ar * w;
+    y.y = (a.sflag[p] ? -ai : ai) * w;  // Eq. (8): folded visibilities are conjugated
+    if (add_i) {
+        C o = vis[a.perm[p]];
+        o.x -= y.y;
+        o.y += y.x;
+        y = o;
+    }
+    vis[a.perm[p]] = y;
+}
+
+// GC_k^dagger (grid) on runs, no atomics: a wavefront accumulates its unit's
+// band of the tile in LDS, streaming the unit's taps (one contiguous range)
+// in slots of 64 consecutive taps with all lanes busy, whatever the run
+// lengths.  Run records are staged 64 at a time; a slot's runs are found
+// with ballots over the staged starts (a 64-bit mask of the taps that start
+// a run, and each lane's count of the starts up to it).  The cells of one
+// run are distinct, but two runs of a slot may share cells, so the slot's
+// read-modify-writes go run by run (masked passes); a wavefront's LDS
+// accesses complete in order.  The band is then stored into the grid (the
+// tile's only item; an empty band is already zero there) or into the item's
+// partial tile, which k_reduce_tiles sums.
+template <bool kFP64, int kBR>
+__global__ __launch_bounds__(64 * kRunWaves) void k_grid_runs(const typename Types<kFP64>::C *__restrict__ taps,
+                                                              const typename Types<kFP64>::C *__restrict__ yw,
+                                                              typename Types<kFP64>::C *grids, RunArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    constexpr int kCells = kBR * kTile;
+    constexpr int kNB = kTile / kBR;
+    __shared__ C s_band[kRunWaves][kCells + 1];  // + a spare cell for lanes without a tap
+    __shared__ int4 s_rec[kRunWaves][kRunChunk];
+    __shared__ C s_y[kRunWaves][kRunChunk];
+    const int wid = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
+    if (u >= a.n_units) return;  // uniform over the wavefront
+    const int r_beg = a.unit_run0[u], r_end = a.unit_run0[u + 1];
+    const int item = (int)(u / kNB), band = (int)(u % kNB);
+    const bool sole = a.item_sole[item] != 0;
+    if (sole && r_beg >= r_end) return;  // nothing to add to a band the zero pass cleared
+    C *sb = s_band[wid];
+    int4 *rec_l = s_rec[wid];
+    C *y_l = s_y[wid];
+    C zero;
+    zero.x = 0;
+    zero.y = 0;
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = zero;
+    const C *tp = taps + a.unit_tap0[u];
+    const int t_unit = (int)(a.unit_tap0[u + 1] - a.unit_tap0[u]);
+    for (int c0 = r_beg; c0 < r_end; c0 += kRunChunk) {
+        const int nrun = (r_end - c0 < kRunChunk) ? r_end - c0 : kRunChunk;
+        wave_fence();  // the previous chunk's records are no longer read
+        int st = 0x7FFFFFFF;  // start of staged run `lane` (past the chunk: never reached)
+        if (lane < nrun) {
+            const int4 rec = a.runrec[c0 + lane];
+            rec_l[lane] = rec;
+            y_l[lane] = yw[rec.z];
+            st = rec.x;
+        }
+        wave_fence();
+        const int t_beg = __builtin_amdgcn_readfirstlane(st);
+        const int t_end = (c0 + nrun < r_end) ? a.runrec[c0 + nrun].x : t_unit;
+        for_batches(t_beg, t_end, [&](int k0, auto ucount) {
+            constexpr int U = decltype(ucount)::value;
+            C K[U];
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int t = k0 + 64 * s + lane;
+                K[s] = load_tap(tp + (t < t_end ? t : t_beg));
+            }
+#pragma unroll
+            for (int s = 0; s < U; ++s) {
+                const int s0 = k0 + 64 * s;
+                if (s0 < t_end) {  // uniform
+                    // staged run holding the slot's first tap, and the run starts inside the slot
+                    const int ra = (int)__popcll(__ballot(st <= s0)) - 1;
+                    uint64_t inside = __ballot(st > s0 && st <= s0 + 63);
+                    const int nstarts = (int)__popcll(inside);
+                    uint64_t tmask = 0;
+                    while (inside) {
+                        const int j = (int)__builtin_ctzll(inside);
+                        inside &= inside - 1;
+                        tmask |= 1ull << (__builtin_amdgcn_readlane(st, j) - s0);
+                    }
+                    const int rel = bits_upto(tmask, lane);
+                    const int t = s0 + lane;
+                    const int4 rec = rec_l[ra + rel];
+                    const C y = y_l[ra + rel];
+                    const int nc = (rec.y >> 16) & 255;
+                    const int local = t - rec.x;
+                    const int row = sub_row(local, recip_nc(nc));
+                    const int cell = t < t_end ? sub_cell(rec.y & 0xFFFF, local, row, nc) : kCells;
+                    const R dx = K[s].x * y.x + K[s].y * y.y;  // conj(K) y
+                    const R dy = K[s].x * y.y - K[s].y * y.x;
+                    for (int j = 0; j <= nstarts; ++j) {  // uniform: one pass per run of the slot
+                        if (rel == j) {
+                            C z = sb[cell];
+                            z.x += dx;
+                            z.y += dy;
+                            sb[cell] = z;
+                        }
+                    }
+                }
+            }
+        });
+    }
+    const uint32_t key = a.item_key[item];
+    C *dst;
+    int64_t ld;
+    if (sole) {
+        dst = tile_origin(grids, key, a.tile_bits, a.G);
+        ld = a.G;
+    } else {
+        dst = (C *)a.partial + (int64_t)a.item_slot[item] * kTile * kTile;
+        ld = kTile;
+    }
+    dst += (int64_t)band * kBR * ld;
+    wave_fence();
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) dst[(int64_t)r * ld + lane] = sb[r * kTile + lane];
+}
+
 // Sum the partial tiles of each tile shared by several items, in the order of
 // the tile's items (deterministic), and store the result in the grid.
 template <bool kFP64>
@@ -1043,6 +1307,22 @@ hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
     return hipSuccess;
 }
 
+RunArgs run_args(const wsp_ctx *c) {
+    const Plan &pl = c->plan;
+    RunArgs r{};
+    r.runrec = pl.runrec;
+    r.unit_run0 = pl.unit_run0;
+    r.unit_tap0 = pl.unit_tap0;
+    r.item_key = pl.item_key;
+    r.item_sole = pl.item_sole;
+    r.item_slot = pl.item_slot;
+    r.partial = c->scratch_part;
+    r.n_units = (int64_t)pl.n_items * pl.tile_bands;
+    r.tile_bits = pl.tile_bits;
+    r.G = c->g.G;
+    return r;
+}
+
 void set_plane_args(const wsp_ctx *c, TileArgs *ta) {
     ta->itile = c->plan.itile;
     if (!c->g.planes) return;
@@ -1071,6 +1351,19 @@ __global__ void k_plane_vis_taps(const double *__restrict__ ux, const double *__
     }
 }
 
+// Test hook: the J_p x J_p taps of sorted visibility sidx, row-major, read
+// from their positions in the band-major layout.
+template <typename C>
+__global__ void k_vis_taps(const C *__restrict__ taps, TapLayout lay, const int32_t *__restrict__ jp,
+                           const int32_t *__restrict__ u0w, const int32_t *__restrict__ v0w, int64_t sidx, C *out) {
+    const int J = jp[sidx];
+    const int uw = u0w[sidx], vw = v0w[sidx];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < J * J; t += gridDim.x * blockDim.x) {
+        const int row = t / J, col = t - row * J;
+        out[t] = taps[tap_position(lay, (int)sidx, row, col, J, uw, vw)];
+    }
+}
+
 template <bool kFP64>
 hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_centres,
                     hipStream_t s, int add_i) {
@@ -1089,27 +1382,41 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     if (e != hipSuccess) return e;
     ApplyArgs a = make_args(c);
     const Plan &pl = c->plan;
+    const C *tp = (const C *)c->taps;
+    const C *gr = (const C *)c->grids;
+    C *dp = (C *)c->scratch_dpart;
+    ev = stage_begin(c, s);
+    if (!g.planes) {
+        const RunArgs ra = run_args(c);
+        if (ra.n_units > 0) {
+            // group width from the mean run length
+            const int64_t mean_run = pl.n_runs > 0 ? pl.total_taps / pl.n_runs : 1;
+            const dim3 gd(blocks(ra.n_units, kRunWaves)), bd(64 * kRunWaves);
+            if (pl.tile_band_rows == 16) {
+                if (mean_run < 48) hipLaunchKernelGGL((k_degrid_runs<kFP64, 8, 16>), gd, bd, 0, s, tp, gr, dp, ra);
+                else if (mean_run < 192) hipLaunchKernelGGL((k_degrid_runs<kFP64, 16, 16>), gd, bd, 0, s, tp, gr, dp, ra);
+                else hipLaunchKernelGGL((k_degrid_runs<kFP64, 64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
+            } else {
+                if (mean_run < 48) hipLaunchKernelGGL((k_degrid_runs<kFP64, 8, 8>), gd, bd, 0, s, tp, gr, dp, ra);
+                else if (mean_run < 192) hipLaunchKernelGGL((k_degrid_runs<kFP64, 16, 8>), gd, bd, 0, s, tp, gr, dp, ra);
+                else hipLaunchKernelGGL((k_degrid_runs<kFP64, 64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
+            }
+        }
+        hipLaunchKernelGGL(k_degrid_reduce_runs<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)dp,
+                           pl.ent_off, pl.run_first, (C *)vis, a, add_i);
+        stage_end(c, kStDegrid, ev, s);
+        return hipGetLastError();
+    }
     TileArgs ta{pl.wrec,      pl.ent_sorted,   pl.item_start, pl.item_key, pl.item_sole,
                 pl.item_slot, c->scratch_part, pl.n_items,    pl.tile_bits, g.G};
     set_plane_args(c, &ta);
-    ev = stage_begin(c, s);
-    if (pl.n_items > 0) {
-        unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        // entries of a few tens of taps (many w-stacks) go four to a wavefront
-        const bool small = pl.total_taps < kSmallEntryTaps * pl.n_entries;
-        const C *tp = (const C *)c->taps;
-        const C *gr = (const C *)c->grids;
-        C *dp = (C *)c->scratch_dpart;
-        if constexpr (!kFP64) {
-            if (g.planes) {
-                if (small) hipLaunchKernelGGL((k_degrid_small<false, true>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
-                else hipLaunchKernelGGL((k_degrid_tiles<false, true>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
-                nb = 0;
-            }
-        }
-        if (nb > 0) {
-            if (small) hipLaunchKernelGGL((k_degrid_small<kFP64, false>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
-            else hipLaunchKernelGGL((k_degrid_tiles<kFP64, false>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
+    if constexpr (!kFP64) {  // w-plane kernels (FP32 path only)
+        if (pl.n_items > 0) {
+            const unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
+            // entries of a few tens of taps (many w-stacks) go four to a wavefront
+            const bool small = pl.total_taps < kSmallEntryTaps * pl.n_entries;
+            if (small) hipLaunchKernelGGL((k_degrid_small<false, true>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
+            else hipLaunchKernelGGL((k_degrid_tiles<false, true>), dim3(nb), dim3(kThreads), 0, s, tp, gr, dp, ta);
         }
     }
     hipLaunchKernelGGL(k_degrid_reduce<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s,
@@ -1136,24 +1443,24 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     hipLaunchKernelGGL(k_prep_vis<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)vis,
                        (C *)c->scratch_yw, a, rot);
     set_plane_args(c, &ta);
-    if (pl.n_items > 0) {
-        unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
-        const bool small = pl.total_taps < kSmallEntryTaps * pl.n_entries;
-        const C *tp = (const C *)c->taps;
-        const C *yw = (const C *)c->scratch_yw;
-        C *gr = (C *)c->grids;
-        const dim3 gs(kGridSplitSmall * nb), bs(kThreads / kGridSplitSmall);
-        const dim3 gt(kGridSplit * nb), bt(kThreads / kGridSplit);
-        if constexpr (!kFP64) {
-            if (g.planes) {
-                if (small) hipLaunchKernelGGL((k_grid_small<false, kGridSplitSmall, true>), gs, bs, 0, s, tp, yw, gr, ta);
-                else hipLaunchKernelGGL((k_grid_tiles<false, kGridSplit, true>), gt, bt, 0, s, tp, yw, gr, ta);
-                nb = 0;
-            }
-        }
-        if (nb > 0) {
-            if (small) hipLaunchKernelGGL((k_grid_small<kFP64, kGridSplitSmall, false>), gs, bs, 0, s, tp, yw, gr, ta);
-            else hipLaunchKernelGGL((k_grid_tiles<kFP64, kGridSplit, false>), gt, bt, 0, s, tp, yw, gr, ta);
+    const C *tp = (const C *)c->taps;
+    const C *yw = (const C *)c->scratch_yw;
+    C *gr = (C *)c->grids;
+    if (!g.planes) {
+        const RunArgs ra = run_args(c);
+        const dim3 gd(blocks(ra.n_units, kRunWaves)), bd(64 * kRunWaves);
+        if (ra.n_units > 0 && pl.tile_band_rows == 16)
+            hipLaunchKernelGGL((k_grid_runs<kFP64, 16>), gd, bd, 0, s, tp, yw, gr, ra);
+        else if (ra.n_units > 0)
+            hipLaunchKernelGGL((k_grid_runs<kFP64, 8>), gd, bd, 0, s, tp, yw, gr, ra);
+    } else if constexpr (!kFP64) {  // w-plane kernels (FP32 path only)
+        if (pl.n_items > 0) {
+            const unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
+            const bool small = pl.total_taps < kSmallEntryTaps * pl.n_entries;
+            const dim3 gs(kGridSplitSmall * nb), bs(kThreads / kGridSplitSmall);
+            const dim3 gt(kGridSplit * nb), bt(kThreads / kGridSplit);
+            if (small) hipLaunchKernelGGL((k_grid_small<false, kGridSplitSmall, true>), gs, bs, 0, s, tp, yw, gr, ta);
+            else hipLaunchKernelGGL((k_grid_tiles<false, kGridSplit, true>), gt, bt, 0, s, tp, yw, gr, ta);
         }
     }
     if (pl.n_mtiles > 0) {
@@ -1184,6 +1491,18 @@ hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s, i
 hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s, int rot) {
     if (c->p.precision == WSP_FP64) return grid_t<true>(c, vis, image, c->plan_centres, s, rot);
     return grid_t<false>(c, vis, image, c->plan_centres, s, rot);
+}
+
+hipError_t run_exact_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s) {
+    const Plan &pl = c->plan;
+    const TapLayout lay{pl.ent_off, pl.run_first, pl.run_tap, pl.tile_band_rows};
+    if (c->p.precision == WSP_FP64)
+        hipLaunchKernelGGL(k_vis_taps<double2>, dim3(64), dim3(256), 0, s, (const double2 *)c->taps, lay, pl.jp,
+                           pl.u0w, pl.v0w, sidx, (double2 *)out_dev);
+    else
+        hipLaunchKernelGGL(k_vis_taps<float2>, dim3(64), dim3(256), 0, s, (const float2 *)c->taps, lay, pl.jp,
+                           pl.u0w, pl.v0w, sidx, (float2 *)out_dev);
+    return hipGetLastError();
 }
 
 hipError_t run_plane_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s) {

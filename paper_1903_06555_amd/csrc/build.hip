@@ -93,6 +93,7 @@ struct BuildArgs {
     const int32_t *jp;
     const int32_t *u0w, *v0w;
     const int64_t *tap_off;
+    TapLayout lay;  // positions of the taps in the band-major layout
     void *taps;
     Geom g;
     double tol;
@@ -372,20 +373,25 @@ __device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, d
             }
             thr = A.tol * S / R;
         }
-        // count the panels to split
+        // count the panels to split; a panel over the tolerance but too narrow
+        // to split (FP32 boundaries) stays whole and marks the visibility capped
         int total = 0;
+        bool floor_hit = false;
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             if (c * kWave < P) {
                 int i = c * kWave + lane;
-                bool sp = false;
+                bool sp = false, over = false;
                 if (i < P && err[c] >= 0.0f) {
                     float wa = fabsf(cur[i]), wb = fabsf(cur[i + 1]);
-                    sp = (double)err[c] > thr * (double)(wb - wa) && (wb - wa) > 4.0e-6f * wb;
+                    over = (double)err[c] > thr * (double)(wb - wa);
+                    sp = over && (wb - wa) > 4.0e-6f * wb;
                 }
                 total += __popcll(__ballot(sp));
+                floor_hit = floor_hit || __ballot(over && !sp) != 0ull;
             }
         }
+        if (floor_hit) *capped = true;
         if (total == 0) break;
         if (P + total > cap) {
             *capped = true;
@@ -485,7 +491,7 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
     const int64_t cbase = (int64_t)(unit - unit_off[i]) * chunk;
 
     double q[kTapsPerLane];
-    float qf[kTapsPerLane], qinv[kTapsPerLane], qrs[kTapsPerLane];
+    float qf[kTapsPerLane], qinv[kTapsPerLane];
     double qinv64[kTapsPerLane], qrs64[kTapsPerLane];
     double accr[kTapsPerLane], acci[kTapsPerLane];
 #pragma unroll
@@ -498,11 +504,8 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         qf[k] = (float)(kTwoPi * q[k]);
         // per-tap factors of 8 / x and sqrt(2 / (pi x)) (unused when q = 0)
         qinv[k] = q[k] > 0.0 ? (float)(1.0 / q[k]) : 0.0f;
-        qrs[k] = q[k] > 0.0 ? (float)(1.0 / sqrt(q[k])) : 0.0f;
-        if constexpr (kFP64) {
-            qinv64[k] = q[k] > 0.0 ? 1.0 / q[k] : 0.0;
-            qrs64[k] = q[k] > 0.0 ? 1.0 / sqrt(q[k]) : 0.0;
-        }
+        qrs64[k] = q[k] > 0.0 ? 1.0 / sqrt(q[k]) : 0.0;
+        if constexpr (kFP64) qinv64[k] = q[k] > 0.0 ? 1.0 / q[k] : 0.0;
         accr[k] = acci[k] = 0.0;
     }
     for (int pg = 0; pg < P; pg += kPanelGroup) {
@@ -548,34 +551,24 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
                 acci[k] += pi_[k];
             }
         } else {
-            // per-node factors, broadcast with readlane (no LDS round trip)
-            const float nref = (float)nre, nimf = (float)nim;
+            // per-node factors, broadcast with readlane (no LDS round trip); the
+            // node weights, the Bessel amplitude and the sums stay in FP64
             const float rinv = nr > 0.0 ? (float)(1.2732395447351627 / nr) : 0.0f;  // (4/pi) / r
-            const float rrs = nr > 0.0 ? (float)(0.3183098861837907 / sqrt(nr)) : 0.0f;  // 1 / (pi sqrt r)
+            const double rrs = nr > 0.0 ? 0.3183098861837907 / sqrt(nr) : 0.0;     // 1 / (pi sqrt r)
             const float nrf = (float)nr;
-            // FP32 partial sums over one panel (15 nodes), accumulated in FP64
-            for (int pb = 0; pb < nn; pb += WSP_GK_N) {
-                float pr[kTapsPerLane], pi_[kTapsPerLane];
-#pragma unroll
-                for (int k = 0; k < kTapsPerLane; ++k) pr[k] = pi_[k] = 0.0f;
-                for (int n = pb; n < pb + WSP_GK_N; ++n) {
-                    const double rn = readlane_f64(nr, n);
-                    const float are = readlane_f32(nref, n), aim = readlane_f32(nimf, n);
-                    const float ri = readlane_f32(rinv, n), rr = readlane_f32(rrs, n);
-                    const float rnf = readlane_f32(nrf, n);
-#pragma unroll
-                    for (int k = 0; k < kTapsPerLane; ++k) {
-                        if (cbase + (int64_t)k * kWave < ntap) {
-                            float J = j0_fp64phase(rn, q[k], rnf * qf[k], ri * qinv[k], rr * qrs[k]);
-                            pr[k] = fmaf(are, J, pr[k]);
-                            pi_[k] = fmaf(aim, J, pi_[k]);
-                        }
-                    }
-                }
+            for (int n = 0; n < nn; ++n) {
+                const double rn = readlane_f64(nr, n);
+                const double are = readlane_f64(nre, n), aim = readlane_f64(nim, n);
+                const float ri = readlane_f32(rinv, n);
+                const double rr = readlane_f64(rrs, n);
+                const float rnf = readlane_f32(nrf, n);
 #pragma unroll
                 for (int k = 0; k < kTapsPerLane; ++k) {
-                    accr[k] += (double)pr[k];
-                    acci[k] += (double)pi_[k];
+                    if (cbase + (int64_t)k * kWave < ntap) {
+                        const double J = j0_fp64phase(rn, q[k], rnf * qf[k], ri * qinv[k], rr * qrs64[k]);
+                        accr[k] = fma(are, J, accr[k]);
+                        acci[k] = fma(aim, J, acci[k]);
+                    }
                 }
             }
         }
@@ -602,14 +595,13 @@ __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int n
         }
         return;
     }
-    const int64_t off = A.tap_off[p];
     const int u0w = A.u0w[p], v0w = A.v0w[p];
 #pragma unroll
     for (int k = 0; k < kTapsPerLane; ++k) {
         int64_t t = cbase + (int64_t)k * kWave + lane;
         if (t < ntap) {
             const int row = (int)(t / jp), col = (int)(t - (int64_t)(t / jp) * jp);
-            const int64_t pos = off + blocked_tap_index(row, col, jp, u0w, v0w);
+            const int64_t pos = tap_position(A.lay, p, row, col, jp, u0w, v0w);
             // with a DDE convolution the w-kernel fills the inner block only
             const bool ring = in_dde_ring(row, col, jp, g.dde_h);
             if constexpr (kFP64) {
@@ -635,7 +627,6 @@ __global__ __launch_bounds__(256) void k_interp(BuildArgs A, int64_t batch0,
     const PointSet ps = point_set(ux, vx, jp, A.sstep, A.inv_sstep);
     if (!ps.sampled) return;  // uniform over the block
     const double2 *smp = samples + samp_off[i];
-    const int64_t off = A.tap_off[p];
     const int u0w = A.u0w[p], v0w = A.v0w[p];
     const int64_t ntap = (int64_t)jp * jp;
     for (int64_t t = threadIdx.x; t < ntap; t += blockDim.x) {
@@ -662,7 +653,7 @@ __global__ __launch_bounds__(256) void k_interp(BuildArgs A, int64_t batch0,
             re = fma(lk, v.x, re);
             im = fma(lk, v.y, im);
         }
-        const int64_t pos = off + blocked_tap_index(row, col, jp, u0w, v0w);
+        const int64_t pos = tap_position(A.lay, p, row, col, jp, u0w, v0w);
         if (in_dde_ring(row, col, jp, A.g.dde_h)) re = im = 0.0;
         if constexpr (kFP64) {
             ((double2 *)A.taps)[pos] = make_double2(re, im);
@@ -689,7 +680,7 @@ __global__ __launch_bounds__(64) void k_dde_conv(BuildArgs A, int64_t batch0) {
     const int64_t cp = A.perm[p];
     const C *du = (const C *)A.dde_u + cp * JD;
     const C *dv = (const C *)A.dde_v + cp * JD;
-    C *taps = (C *)A.taps + A.tap_off[p];
+    C *taps = (C *)A.taps;
     const int u0w = A.u0w[p], v0w = A.v0w[p];
     const int lane = threadIdx.x;
     for (int r = -h; r < J; ++r) {
@@ -703,7 +694,7 @@ __global__ __launch_bounds__(64) void k_dde_conv(BuildArgs A, int64_t batch0) {
                 for (int a = -h; a <= h; ++a) {
                     const int cc = c - a;
                     if (cc < 0 || cc >= J) continue;
-                    const C k = taps[blocked_tap_index(hr, cc, J, u0w, v0w)];
+                    const C k = taps[tap_position(A.lay, p, hr, cc, J, u0w, v0w)];
                     const C d = du[a + h];
                     acc.x += d.x * k.x - d.y * k.y;
                     acc.y += d.x * k.y + d.y * k.x;
@@ -725,7 +716,7 @@ __global__ __launch_bounds__(64) void k_dde_conv(BuildArgs A, int64_t batch0) {
                     acc.x += d.x * hv.x - d.y * hv.y;
                     acc.y += d.x * hv.y + d.y * hv.x;
                 }
-                taps[blocked_tap_index(r, c, J, u0w, v0w)] = acc;
+                taps[tap_position(A.lay, p, r, c, J, u0w, v0w)] = acc;
             }
         }
         __syncthreads();
@@ -853,15 +844,15 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
     size_t tmp_bytes = 0;
     auto cleanup = [&]() {
         if (ws) return;  // carved from the caller's region: nothing to free
-        hipFree(part);
-        hipFree(npan);
-        hipFree(cnt);
-        hipFree(uoff);
-        hipFree(scnt);
-        hipFree(soff);
-        hipFree(samples);
-        hipFree(tmp2);
-        hipFree(tmp);
+        dfree(part);
+        dfree(npan);
+        dfree(cnt);
+        dfree(uoff);
+        dfree(scnt);
+        dfree(soff);
+        dfree(samples);
+        dfree(tmp2);
+        dfree(tmp);
     };
 #define WSP_BSTEP(expr)        \
     do {                       \
@@ -896,16 +887,16 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
         samples = (double2 *)q;
         samples_cap = (int64_t)(L.samples / sizeof(double2));
     } else {
-        WSP_BSTEP(hipMalloc(&part, sizeof(float) * (size_t)B * (kMaxPanels + 2)));
-        WSP_BSTEP(hipMalloc(&npan, sizeof(int) * (size_t)B));
-        WSP_BSTEP(hipMalloc(&cnt, sizeof(int) * (size_t)(B + 1)));
-        WSP_BSTEP(hipMalloc(&scnt, sizeof(int64_t) * (size_t)(B + 1)));
-        WSP_BSTEP(hipMalloc(&soff, sizeof(int64_t) * (size_t)(B + 1)));
+        WSP_BSTEP(dmalloc(&part, sizeof(float) * (size_t)B * (kMaxPanels + 2)));
+        WSP_BSTEP(dmalloc(&npan, sizeof(int) * (size_t)B));
+        WSP_BSTEP(dmalloc(&cnt, sizeof(int) * (size_t)(B + 1)));
+        WSP_BSTEP(dmalloc(&scnt, sizeof(int64_t) * (size_t)(B + 1)));
+        WSP_BSTEP(dmalloc(&soff, sizeof(int64_t) * (size_t)(B + 1)));
         WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2_bytes, scnt, soff, B + 1, s));
-        WSP_BSTEP(hipMalloc(&tmp2, tmp2_bytes));
-        WSP_BSTEP(hipMalloc(&uoff, sizeof(int) * (size_t)(B + 1)));
+        WSP_BSTEP(dmalloc(&tmp2, tmp2_bytes));
+        WSP_BSTEP(dmalloc(&uoff, sizeof(int) * (size_t)(B + 1)));
         WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, uoff, B + 1, s));
-        WSP_BSTEP(hipMalloc(&tmp, tmp_bytes));
+        WSP_BSTEP(dmalloc(&tmp, tmp_bytes));
     }
     for (int64_t b0 = first; b0 < end; b0 += B) {
         int nb = (int)(end - b0 < B ? end - b0 : B);
@@ -930,10 +921,10 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
                 cleanup();
                 return e;
             }
-            hipFree(samples);
+            dfree(samples);
             samples = nullptr;
             samples_cap = 0;
-            WSP_BSTEP(hipMalloc(&samples, sizeof(double2) * (size_t)nsamp));
+            WSP_BSTEP(dmalloc(&samples, sizeof(double2) * (size_t)nsamp));
             samples_cap = nsamp;
         }
         dim3 grid((unsigned)((nunits + kWavesPerBlock - 1) / kWavesPerBlock));
@@ -969,7 +960,10 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
 BuildArgs common_args(wsp_ctx *c) {
     BuildArgs A{};
     A.g = c->g;
-    A.tol = c->p.quad_abs_tol > 0.0 ? c->p.quad_abs_tol : c->p.quad_rel_tol;
+    // both tolerances are relative to the visibility's kernel peak: the
+    // tighter positive one decides
+    const double ta = c->p.quad_abs_tol, tr = c->p.quad_rel_tol;
+    A.tol = (ta > 0.0 && tr > 0.0) ? (ta < tr ? ta : tr) : (ta > 0.0 ? ta : tr);
     A.max_panels = c->p.quad_max_panels;
     A.stats = c->plan.stats;
     const bool fp64 = c->p.precision == WSP_FP64;
@@ -992,6 +986,7 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s,
     A.u0w = pl.u0w;
     A.v0w = pl.v0w;
     A.tap_off = pl.tap_off;
+    A.lay = TapLayout{pl.ent_off, pl.run_first, pl.run_tap, pl.tile_band_rows};
     A.taps = c->taps;
     A.dde_u = c->dde_u;
     A.dde_v = c->dde_v;
@@ -1019,6 +1014,16 @@ int build_batch_in(const wsp_ctx *c, size_t cap) {
     int B = 0;
     if (fitting_batch(c, A, count, cap, &B) != hipSuccess) return 0;
     return B;
+}
+
+// Peak bytes the allocating build holds at once (its batch temporaries).
+size_t build_temp_bytes(const wsp_ctx *c) {
+    const BuildArgs A = common_args(const_cast<wsp_ctx *>(c));
+    const int64_t count = c->g.planes ? (int64_t)c->plan.n_pairs + 1 : c->plan.m;
+    const int B = (int)(count < kBuildBatch ? count : kBuildBatch);
+    WsLayout L;
+    if (ws_layout(B, batch_samples_bound(c, c->g.planes, A.inv_sstep, B), &L) != hipSuccess) return 0;
+    return L.total;
 }
 
 // ---- static build workspace ----------------------------------------------------------

@@ -12,6 +12,9 @@
 
 namespace wsp {
 
+// mean taps per entry below which a plan uses bands of 16 rows
+constexpr int64_t kSmallEntryTapsPlan = 160;
+
 namespace {
 
 #define WSP_TRY(expr)                         \
@@ -237,7 +240,7 @@ inline unsigned grid1d(int64_t n, int block) { return (unsigned)((n + block - 1)
 
 template <typename T>
 hipError_t dalloc(T **p, size_t count) {
-    return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+    return dmalloc((void **)p, sizeof(T) * (count ? count : 1));
 }
 
 // ------------------------------------------------ tile work lists ---------
@@ -370,15 +373,15 @@ __global__ void k_seg_base_cand(const int64_t *__restrict__ incl, const int64_t 
 // start crosses a multiple of kItemTaps.
 __global__ void k_item_head(const int64_t *__restrict__ incl, const int64_t *__restrict__ work,
                             const int64_t *__restrict__ segbase, const uint8_t *__restrict__ head,
-                            int64_t E, uint8_t *ihead) {
+                            int64_t E, int64_t item_taps, uint8_t *ihead) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= E) return;
     if (head[s]) {
         ihead[s] = 1;
         return;
     }
-    int64_t c = (incl[s] - work[s] - segbase[s]) / kItemTaps;
-    int64_t cp = (incl[s - 1] - work[s - 1] - segbase[s - 1]) / kItemTaps;
+    int64_t c = (incl[s] - work[s] - segbase[s]) / item_taps;
+    int64_t cp = (incl[s - 1] - work[s - 1] - segbase[s - 1]) / item_taps;
     ihead[s] = c != cp ? 1 : 0;
 }
 
@@ -391,7 +394,180 @@ __global__ void k_item_info(const int32_t *__restrict__ item_start, int n_items,
     if (i == n_items - 1) *item_start_out_last = (int32_t)E;
 }
 
+// ------------------------------------------- band-major tap layout -------
+// Bands [b0, b0 + nb) of br tile rows that an entry covers.
+__device__ __forceinline__ void entry_bands(int z, int br, int *b0, int *nb) {
+    const int nr = (z >> 8) & 255, ly0 = (z >> 24) & 255;
+    *b0 = ly0 / br;
+    *nb = (ly0 + nr - 1) / br - *b0 + 1;
+}
+
+__global__ void k_run_counts(const int4 *__restrict__ ent, int64_t E, int br, int32_t *cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > E) return;
+    if (e == E) {
+        cnt[e] = 0;
+        return;
+    }
+    int b0, nb;
+    entry_bands(ent[e].z, br, &b0, &nb);
+    cnt[e] = nb;
+}
+
+__global__ void k_pos_of(const int32_t *__restrict__ ent_sorted, int64_t E, int32_t *pos_of) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < E) pos_of[ent_sorted[s]] = (int32_t)s;
+}
+
+// marks[item_start[i]] = 1 for i >= 1 (an inclusive scan then gives each
+// work position its item)
+__global__ void k_item_marks(const int32_t *__restrict__ item_start, int n_items, int32_t *marks) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 1 && i < n_items) marks[item_start[i]] = 1;
+}
+
+// Runs in generation order: sort key (item, band, work position) and tap count.
+__global__ void k_run_keys(const int4 *__restrict__ ent, const int32_t *__restrict__ run_first,
+                           const int32_t *__restrict__ pos_of, const int32_t *__restrict__ item_of_pos,
+                           int64_t E, int br, uint64_t *key, int32_t *gidx, int32_t *rlen) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int z = ent[e].z;
+    const int nc = z & 255, nr = (z >> 8) & 255, ly0 = (z >> 24) & 255;
+    int b0, nb;
+    entry_bands(z, br, &b0, &nb);
+    const int32_t s = pos_of[e];
+    const uint64_t it = (uint64_t)item_of_pos[s];
+    for (int k = 0; k < nb; ++k) {
+        const int b = b0 + k;
+        const int g = run_first[e] + k;
+        const int lo = ly0 > b * br ? ly0 : b * br;
+        const int hi = (ly0 + nr < (b + 1) * br) ? ly0 + nr : (b + 1) * br;
+        key[g] = (it << 35) | ((uint64_t)b << 31) | (uint64_t)(uint32_t)s;
+        gidx[g] = g;
+        rlen[g] = (hi - lo) * nc;
+    }
+}
+
+__device__ __forceinline__ int64_t run_unit(uint64_t key, int bands) {
+    return (int64_t)(key >> 35) * bands + (int64_t)((key >> 31) & 15);
+}
+
+__global__ void k_run_lengths(const int32_t *__restrict__ lay2gen, const int32_t *__restrict__ rlen,
+                              int64_t R, int64_t *len_lay) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L > R) return;
+    len_lay[L] = L == R ? 0 : rlen[lay2gen[L]];
+}
+
+__global__ void k_run_taps(const int32_t *__restrict__ lay2gen, const int64_t *__restrict__ start_lay,
+                           int64_t R, int64_t *run_tap) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L < R) run_tap[lay2gen[L]] = start_lay[L];
+}
+
+// First run of each unit (units without runs take the next unit's first run).
+__global__ void k_unit_heads(const uint64_t *__restrict__ keys, int64_t R, int64_t U, int bands,
+                             int32_t *unit_run0) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= R) return;
+    const int64_t u = run_unit(keys[L], bands);
+    const int64_t up = L == 0 ? -1 : run_unit(keys[L - 1], bands);
+    for (int64_t v = up + 1; v <= u; ++v) unit_run0[v] = (int32_t)L;
+    if (L == R - 1)
+        for (int64_t v = u + 1; v <= U; ++v) unit_run0[v] = (int32_t)R;
+}
+
+__global__ void k_unit_taps(const int32_t *__restrict__ unit_run0, const int64_t *__restrict__ start_lay,
+                            int64_t U, int64_t *unit_tap0) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u <= U) unit_tap0[u] = start_lay[unit_run0[u]];
+}
+
+__global__ void k_run_records(const uint64_t *__restrict__ keys, const int32_t *__restrict__ lay2gen,
+                              const int64_t *__restrict__ start_lay, const int64_t *__restrict__ unit_tap0,
+                              const int32_t *__restrict__ ent_sorted, const int4 *__restrict__ ent, int64_t R,
+                              int br, int4 *runrec) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= R) return;
+    const uint64_t key = keys[L];
+    const int b = (int)((key >> 31) & 15);
+    const int4 en = ent[ent_sorted[(int64_t)(key & 0x7FFFFFFFull)]];
+    const int z = en.z;
+    const int nc = z & 255, nr = (z >> 8) & 255, lx0 = (z >> 16) & 255, ly0 = (z >> 24) & 255;
+    const int lo = ly0 > b * br ? ly0 : b * br;
+    const int hi = (ly0 + nr < (b + 1) * br) ? ly0 + nr : (b + 1) * br;
+    const int cell0 = (lo - b * br) * kTile + lx0;
+    runrec[L] = make_int4((int)(start_lay[L] - unit_tap0[run_unit(key, kTile / br)]),
+                          cell0 | (nc << 16) | ((hi - lo) << 24), en.x, lay2gen[L]);
+}
+
+// Touched cells: every row of an entry covers columns lx0 .. lx0 + nc - 1 of
+// one tile row, a bit range of that tile row's 64-bit word.
+__global__ void k_touched_rows(const int4 *__restrict__ ent, int64_t E, unsigned long long *words) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int4 en = ent[e];
+    const int nc = en.z & 255, nr = (en.z >> 8) & 255, lx0 = (en.z >> 16) & 255, ly0 = (en.z >> 24) & 255;
+    const unsigned long long bits = (nc >= 64 ? ~0ull : ((1ull << nc) - 1ull)) << lx0;
+    unsigned long long *w = words + (int64_t)(uint32_t)en.w * kTile + ly0;
+    for (int r = 0; r < nr; ++r) atomicOr(w + r, bits);
+}
+
+__global__ void k_popcount_sum(const unsigned long long *__restrict__ words, int64_t n,
+                               unsigned long long *total) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += (unsigned long long)__popcll(words[i]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(total, c);
+}
+
+__global__ void k_find_index(const int32_t *__restrict__ perm, int64_t m, int32_t p, int64_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m && perm[i] == p) *out = i;  // perm is a permutation: one writer
+}
+
 }  // namespace
+
+hipError_t find_sorted_index(const wsp_ctx *c, int64_t p, int64_t *sidx) {
+    int64_t *d = nullptr;
+    *sidx = -1;
+    hipError_t e = dmalloc(&d, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMemcpy(d, sidx, sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_find_index, dim3(grid1d(c->plan.m, 256)), dim3(256), 0, 0, c->plan.perm, c->plan.m,
+                           (int32_t)p, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(sidx, d, sizeof(int64_t), hipMemcpyDeviceToHost);
+    dfree(d);
+    return e;
+}
+
+hipError_t count_touched_cells(const wsp_ctx *c, int64_t *cells) {
+    const Plan &pl = c->plan;
+    int stack_bits = 0;
+    while ((1 << stack_bits) < c->g.n_stacks) ++stack_bits;
+    const int64_t n_words = ((int64_t)1 << (2 * pl.tile_bits + stack_bits)) * kTile;
+    unsigned long long *words = nullptr, *total = nullptr;
+    hipError_t e = dmalloc(&words, sizeof(unsigned long long) * (size_t)n_words);
+    if (e == hipSuccess) e = dmalloc(&total, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(words, 0, sizeof(unsigned long long) * (size_t)n_words);
+    if (e == hipSuccess) e = hipMemset(total, 0, sizeof(unsigned long long));
+    if (e == hipSuccess && pl.n_entries > 0) {
+        hipLaunchKernelGGL(k_touched_rows, dim3(grid1d(pl.n_entries, 256)), dim3(256), 0, 0, pl.ent,
+                           pl.n_entries, words);
+        hipLaunchKernelGGL(k_popcount_sum, dim3(1024), dim3(256), 0, 0, words, n_words, total);
+        e = hipGetLastError();
+    }
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpy(&h, total, sizeof(h), hipMemcpyDeviceToHost);
+    dfree(words);
+    dfree(total);
+    *cells = (int64_t)h;
+    return e;
+}
 
 hipError_t launch_fold(const double *uvw, const double *wts, int64_t m, int fold, Plan &pl,
                        int *d_bad, hipStream_t s) {
@@ -403,12 +579,12 @@ hipError_t launch_fold(const double *uvw, const double *wts, int64_t m, int fold
 hipError_t minmax_w(const Plan &pl, double *wmin, double *wmax, hipStream_t s) {
     const int nblk = 512;
     double *d = nullptr;
-    WSP_TRY(hipMalloc(&d, sizeof(double) * 2 * nblk));
+    WSP_TRY(dmalloc(&d, sizeof(double) * 2 * nblk));
     hipLaunchKernelGGL(k_minmax, dim3(nblk), dim3(kRedBlock), 0, s, pl.w, pl.m, d, d + nblk);
     std::vector<double> h(2 * nblk);
     hipError_t e = hipMemcpyAsync(h.data(), d, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(d);
+    dfree(d);
     if (e != hipSuccess) return e;
     double lo = INFINITY, hi = -INFINITY;
     for (int b = 0; b < nblk; ++b) {
@@ -426,9 +602,9 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K, doub
     const int nblk = (int)((pl.m + per - 1) / per);
     double *psum = nullptr, *dnew = nullptr;
     unsigned long long *pcnt = nullptr;
-    WSP_TRY(hipMalloc(&psum, sizeof(double) * (size_t)nblk * K));
-    WSP_TRY(hipMalloc(&pcnt, sizeof(unsigned long long) * (size_t)nblk * K));
-    WSP_TRY(hipMalloc(&dnew, sizeof(double) * K));
+    WSP_TRY(dmalloc(&psum, sizeof(double) * (size_t)nblk * K));
+    WSP_TRY(dmalloc(&pcnt, sizeof(unsigned long long) * (size_t)nblk * K));
+    WSP_TRY(dmalloc(&dnew, sizeof(double) * K));
     hipLaunchKernelGGL(k_kmeans_assign, dim3(nblk), dim3(kRedBlock), 0, s, pl.w, pl.m, d_centres,
                        K, pl.label, psum, pcnt);
     hipLaunchKernelGGL(k_kmeans_reduce, dim3(1), dim3(64 * ((K + 63) / 64)), 0, s, psum, pcnt,
@@ -436,9 +612,9 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K, doub
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h_new, dnew, sizeof(double) * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(psum);
-    hipFree(pcnt);
-    hipFree(dnew);
+    dfree(psum);
+    dfree(pcnt);
+    dfree(dnew);
     return e;
 }
 
@@ -447,7 +623,7 @@ void free_sorted_plan(Plan &pl) {
                     pl.jp,     pl.u0w,     pl.v0w,        pl.stack,    pl.sflag,
                     pl.tap_off, pl.border, pl.stats,      pl.ent,      pl.ent_off,
                     pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole, pl.wrec};
-    for (void *q : ptrs) hipFree(q);
+    for (void *q : ptrs) dfree(q);
     pl.perm = nullptr;
     pl.ux = pl.vx = pl.weff = pl.wt = nullptr;
     pl.jp = pl.u0w = pl.v0w = pl.stack = pl.border = nullptr;
@@ -462,19 +638,25 @@ void free_sorted_plan(Plan &pl) {
     pl.item_sole = nullptr;
     pl.n_entries = 0;
     pl.n_items = 0;
-    hipFree(pl.item_slot);
-    hipFree(pl.mt_first);
-    hipFree(pl.itile);
+    dfree(pl.item_slot);
+    dfree(pl.mt_first);
+    dfree(pl.itile);
     pl.item_slot = pl.mt_first = pl.itile = nullptr;
     pl.n_multi = pl.n_mtiles = 0;
-    hipFree(pl.plane_off);
-    hipFree(pl.prec);
-    hipFree(pl.ptw);
+    dfree(pl.plane_off);
+    dfree(pl.prec);
+    dfree(pl.ptw);
     pl.plane_off = nullptr;
     pl.prec = nullptr;
     pl.ptw = nullptr;
     pl.n_pairs = 0;
     pl.table_len = 0;
+    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec, pl.unit_run0, pl.unit_tap0};
+    for (void *q : rptrs) dfree(q);
+    pl.run_first = pl.unit_run0 = nullptr;
+    pl.run_tap = pl.unit_tap0 = nullptr;
+    pl.runrec = nullptr;
+    pl.n_runs = 0;
 }
 
 // ---- w-plane mode ---------------------------------------------------------------
@@ -527,7 +709,7 @@ hipError_t plane_layout(wsp_ctx *c, hipStream_t s, bool *too_large) {
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&h_max, d_max, sizeof(h_max), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(d_max);
+    dfree(d_max);
     if (e != hipSuccess) return e;
     double wmax;
     static_assert(sizeof(wmax) == sizeof(h_max), "bit pattern");
@@ -598,7 +780,7 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
         void *ptrs[] = {cnt, work, incl, cand, segbase, keys, keys_sorted, iota, d_nsel, head, ihead, tmp};
-        for (void *q : ptrs) hipFree(q);
+        for (void *q : ptrs) dfree(q);
     };
 #define WSP_ESTEP(expr)        \
     do {                       \
@@ -610,10 +792,10 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     } while (0)
     auto scratch = [&](size_t need) -> hipError_t {
         if (need <= tmp_bytes && tmp) return hipSuccess;
-        hipFree(tmp);
+        dfree(tmp);
         tmp = nullptr;
         tmp_bytes = need;
-        return hipMalloc(&tmp, need ? need : 1);
+        return dmalloc(&tmp, need ? need : 1);
     };
     size_t need = 0;
 
@@ -673,8 +855,8 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
             e2 = hipGetLastError();
         }
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);  // before k64 / k64s are released
-        hipFree(k64);
-        hipFree(k64s);
+        dfree(k64);
+        dfree(k64s);
         WSP_ESTEP(e2);
     } else {
         need = 0;
@@ -685,7 +867,7 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
                                                      (int)E, 0, key_bits, s));
     }
 
-    // work items: cut each tile's entries every kItemTaps taps
+    // work items: cut each tile's entries every g.item_taps taps
     WSP_ESTEP(dalloc(&work, E));
     WSP_ESTEP(dalloc(&incl, E));
     WSP_ESTEP(dalloc(&cand, E));
@@ -694,9 +876,11 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     WSP_ESTEP(dalloc(&ihead, E));
     hipLaunchKernelGGL(k_entry_work, dim3(grid1d(E, 256)), dim3(256), 0, s, keys_sorted,
                        pl.ent_sorted, pl.ent, E, work, head);
-    WSP_ESTEP(dalloc(&pl.wrec, E));
-    hipLaunchKernelGGL(k_entry_records, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent_sorted, pl.ent,
-                       pl.tap_off, pl.jp, E, pl.wrec);
+    if (g.planes) {  // entry records of the w-plane kernels
+        WSP_ESTEP(dalloc(&pl.wrec, E));
+        hipLaunchKernelGGL(k_entry_records, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent_sorted, pl.ent,
+                           pl.tap_off, pl.jp, E, pl.wrec);
+    }
     need = 0;
     WSP_ESTEP(hipcub::DeviceScan::InclusiveSum(nullptr, need, work, incl, (int)E, s));
     WSP_ESTEP(scratch(need));
@@ -708,7 +892,7 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     WSP_ESTEP(scratch(need));
     WSP_ESTEP(hipcub::DeviceScan::InclusiveScan(tmp, need, cand, segbase, hipcub::Max(), (int)E, s));
     hipLaunchKernelGGL(k_item_head, dim3(grid1d(E, 256)), dim3(256), 0, s, incl, work, segbase,
-                       head, E, ihead);
+                       head, E, g.item_taps, ihead);
     WSP_ESTEP(hipGetLastError());
     // item starts = indices s with ihead[s] = 1 (at most E items)
     WSP_ESTEP(dalloc(&pl.item_start, E + 1));
@@ -790,10 +974,10 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
         if (e == hipSuccess)
             e = hipMemcpyAsync(pl.mt_first + nmt, &nsel, sizeof(int), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        hipFree(shared_pos);
-        hipFree(slot_pos);
-        hipFree(iks);
-        hipFree(iiota);
+        dfree(shared_pos);
+        dfree(slot_pos);
+        dfree(iks);
+        dfree(iiota);
         WSP_ESTEP(e);
         pl.n_mtiles = nmt;
         pl.n_multi = nmulti;
@@ -801,6 +985,116 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
     cleanup();
     return hipSuccess;
 #undef WSP_ESTEP
+}
+
+// Runs and the band-major tap layout (see Plan), after the work lists.
+static hipError_t make_runs(Plan &pl, hipStream_t s) {
+    const int64_t E = pl.n_entries;
+    const int br = pl.tile_band_rows;
+    const int64_t U = (int64_t)pl.n_items * pl.tile_bands;
+    int32_t *pos_of = nullptr, *marks = nullptr, *item_of_pos = nullptr, *gidx = nullptr,
+            *lay2gen = nullptr, *rlen = nullptr;
+    uint64_t *key = nullptr, *key_sorted = nullptr;
+    int64_t *len_lay = nullptr, *start_lay = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        void *ptrs[] = {pos_of, marks, item_of_pos, gidx, lay2gen, rlen, key, key_sorted, len_lay, start_lay, tmp};
+        for (void *q : ptrs) dfree(q);
+    };
+#define WSP_RSTEP(expr)        \
+    do {                       \
+        e = (expr);            \
+        if (e != hipSuccess) { \
+            cleanup();         \
+            return e;          \
+        }                      \
+    } while (0)
+    auto scratch = [&](size_t need) -> hipError_t {
+        if (need <= tmp_bytes && tmp) return hipSuccess;
+        dfree(tmp);
+        tmp = nullptr;
+        tmp_bytes = need;
+        return dmalloc(&tmp, need ? need : 1);
+    };
+    size_t need = 0;
+    // runs per entry, and each entry's first run (generation order)
+    int32_t *cnt = nullptr;
+    WSP_RSTEP(dalloc(&cnt, E + 1));
+    marks = cnt;  // released by cleanup
+    WSP_RSTEP(dalloc(&pl.run_first, E + 1));
+    hipLaunchKernelGGL(k_run_counts, dim3(grid1d(E + 1, 256)), dim3(256), 0, s, pl.ent, E, br, cnt);
+    WSP_RSTEP(hipGetLastError());
+    WSP_RSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, need, cnt, pl.run_first, (int)(E + 1), s));
+    WSP_RSTEP(scratch(need));
+    WSP_RSTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need, cnt, pl.run_first, (int)(E + 1), s));
+    int32_t R32 = 0;
+    WSP_RSTEP(hipMemcpyAsync(&R32, pl.run_first + E, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    WSP_RSTEP(hipStreamSynchronize(s));
+    const int64_t R = R32;
+    pl.n_runs = R;
+    // work position of each entry, item of each work position
+    WSP_RSTEP(dalloc(&pos_of, E));
+    WSP_RSTEP(dalloc(&item_of_pos, E));
+    hipLaunchKernelGGL(k_pos_of, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent_sorted, E, pos_of);
+    WSP_RSTEP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)(E + 1), s));
+    hipLaunchKernelGGL(k_item_marks, dim3(grid1d(pl.n_items, 256)), dim3(256), 0, s, pl.item_start, pl.n_items,
+                       cnt);
+    WSP_RSTEP(hipGetLastError());
+    need = 0;
+    WSP_RSTEP(hipcub::DeviceScan::InclusiveSum(nullptr, need, cnt, item_of_pos, (int)E, s));
+    WSP_RSTEP(scratch(need));
+    WSP_RSTEP(hipcub::DeviceScan::InclusiveSum(tmp, need, cnt, item_of_pos, (int)E, s));
+    // runs in generation order, sorted into layout order
+    WSP_RSTEP(dalloc(&key, R));
+    WSP_RSTEP(dalloc(&key_sorted, R));
+    WSP_RSTEP(dalloc(&gidx, R));
+    WSP_RSTEP(dalloc(&lay2gen, R));
+    WSP_RSTEP(dalloc(&rlen, R));
+    hipLaunchKernelGGL(k_run_keys, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent, pl.run_first, pos_of,
+                       item_of_pos, E, br, key, gidx, rlen);
+    WSP_RSTEP(hipGetLastError());
+    int item_bits = 1;
+    while (((int64_t)1 << item_bits) < (int64_t)pl.n_items) ++item_bits;
+    need = 0;
+    WSP_RSTEP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key, key_sorted, gidx, lay2gen, (int)R, 0,
+                                                 35 + item_bits, s));
+    WSP_RSTEP(scratch(need));
+    WSP_RSTEP(hipcub::DeviceRadixSort::SortPairs(tmp, need, key, key_sorted, gidx, lay2gen, (int)R, 0,
+                                                 35 + item_bits, s));
+    // tap offsets in layout order
+    WSP_RSTEP(dalloc(&len_lay, R + 1));
+    WSP_RSTEP(dalloc(&start_lay, R + 1));
+    WSP_RSTEP(dalloc(&pl.run_tap, R));
+    hipLaunchKernelGGL(k_run_lengths, dim3(grid1d(R + 1, 256)), dim3(256), 0, s, lay2gen, rlen, R, len_lay);
+    WSP_RSTEP(hipGetLastError());
+    need = 0;
+    WSP_RSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, need, len_lay, start_lay, (int)(R + 1), s));
+    WSP_RSTEP(scratch(need));
+    WSP_RSTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need, len_lay, start_lay, (int)(R + 1), s));
+    hipLaunchKernelGGL(k_run_taps, dim3(grid1d(R, 256)), dim3(256), 0, s, lay2gen, start_lay, R, pl.run_tap);
+    // units
+    WSP_RSTEP(dalloc(&pl.unit_run0, U + 1));
+    WSP_RSTEP(dalloc(&pl.unit_tap0, U + 1));
+    if (R > 0) {
+        hipLaunchKernelGGL(k_unit_heads, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, R, U, pl.tile_bands,
+                           pl.unit_run0);
+    } else {
+        WSP_RSTEP(hipMemsetAsync(pl.unit_run0, 0, sizeof(int32_t) * (size_t)(U + 1), s));
+    }
+    hipLaunchKernelGGL(k_unit_taps, dim3(grid1d(U + 1, 256)), dim3(256), 0, s, pl.unit_run0, start_lay, U,
+                       pl.unit_tap0);
+    WSP_RSTEP(dalloc(&pl.runrec, R));
+    hipLaunchKernelGGL(k_run_records, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, lay2gen, start_lay,
+                       pl.unit_tap0, pl.ent_sorted, pl.ent, R, br, pl.runrec);
+    WSP_RSTEP(hipGetLastError());
+    int64_t total = 0;
+    WSP_RSTEP(hipMemcpyAsync(&total, start_lay + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    WSP_RSTEP(hipStreamSynchronize(s));  // before the temporaries are released
+    cleanup();
+    return total == pl.total_taps ? hipSuccess : hipErrorUnknown;  // every tap in exactly one run
+#undef WSP_RSTEP
 }
 
 hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *support_err) {
@@ -827,21 +1121,21 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     size_t tmp_bytes = 0;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
-        hipFree(t.ux);
-        hipFree(t.vx);
-        hipFree(t.weff);
-        hipFree(t.jp);
-        hipFree(t.u0w);
-        hipFree(t.v0w);
-        hipFree(t.key);
-        hipFree(key_sorted);
-        hipFree(cost);
-        hipFree(cost_sorted);
-        hipFree(iota);
-        hipFree(order_tmp);
-        hipFree(cnt);
-        hipFree(d_err);
-        hipFree(tmp);
+        dfree(t.ux);
+        dfree(t.vx);
+        dfree(t.weff);
+        dfree(t.jp);
+        dfree(t.u0w);
+        dfree(t.v0w);
+        dfree(t.key);
+        dfree(key_sorted);
+        dfree(cost);
+        dfree(cost_sorted);
+        dfree(iota);
+        dfree(order_tmp);
+        dfree(cnt);
+        dfree(d_err);
+        dfree(tmp);
     };
 #define WSP_STEP(expr)                 \
     do {                               \
@@ -881,10 +1175,10 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     hipLaunchKernelGGL(k_iota, dim3(grid1d(m, 256)), dim3(256), 0, s, iota, m);
     WSP_STEP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, t.key, key_sorted, iota,
                                                 pl.perm, (int)m, 0, key_bits > 0 ? key_bits : 1, s));
-    WSP_STEP(hipMalloc(&tmp, tmp_bytes));
+    WSP_STEP(dmalloc(&tmp, tmp_bytes));
     WSP_STEP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, t.key, key_sorted, iota, pl.perm,
                                                 (int)m, 0, key_bits > 0 ? key_bits : 1, s));
-    hipFree(tmp);
+    dfree(tmp);
     tmp = nullptr;
 
     WSP_STEP(dalloc(&pl.ux, m));
@@ -920,15 +1214,15 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     WSP_STEP(hipGetLastError());
     tmp_bytes = 0;
     WSP_STEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, pl.tap_off, (int)(m + 1), s));
-    WSP_STEP(hipMalloc(&tmp, tmp_bytes));
+    WSP_STEP(dmalloc(&tmp, tmp_bytes));
     WSP_STEP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, pl.tap_off, (int)(m + 1), s));
-    hipFree(tmp);
+    dfree(tmp);
     tmp = nullptr;
     hipLaunchKernelGGL(k_iota, dim3(grid1d(m, 256)), dim3(256), 0, s, iota, m);
     tmp_bytes = 0;
     WSP_STEP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, cost, cost_sorted, iota,
                                                 pl.border, (int)m, 0, 32, s));
-    WSP_STEP(hipMalloc(&tmp, tmp_bytes));
+    WSP_STEP(dmalloc(&tmp, tmp_bytes));
     WSP_STEP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, cost, cost_sorted, iota,
                                                 pl.border, (int)m, 0, 32, s));
     int64_t total = 0;
@@ -952,7 +1246,15 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
             return hipSuccess;
         }
     }
-    return make_entries(pl, g, tile_bits, s);
+    hipError_t e3 = make_entries(pl, g, tile_bits, s);
+    if (e3 != hipSuccess || g.planes) return e3;
+    // bands of 16 rows when entries are small (a few stacks' worth of taps),
+    // so that a run holds most of its entry; 8 rows otherwise
+    pl.tile_band_rows = g.band_rows_param > 0 ? g.band_rows_param
+                                              : (pl.total_taps < kSmallEntryTapsPlan * pl.n_entries ? 16 : 8);
+    pl.tile_bands = kTile / pl.tile_band_rows;
+    if (pl.n_entries >= 0x7FFFFFF0LL / pl.tile_bands) return hipErrorInvalidValue;  // run indices are int32
+    return make_runs(pl, s);
 #undef WSP_STEP
 }
 

@@ -122,22 +122,31 @@ __device__ __forceinline__ double j0_fp64(double r, double q, double inv, double
     return amp * (P * cs - Q * sn);
 }
 
-// J0(2 pi r q) for the FP32 path.
+// J0(2 pi r q) for the FP32 path, returned in FP64 for FP64 accumulation.
 //   x < 8:  Chebyshev series in FP64 (no transcendental; an FP64 FMA issues
 //           at the FP32 rate on CDNA without packed math);
-//   x >= 8: Hankel form sqrt(2/(pi x)) (P0 cos(x - pi/4) - Q0 sin(x - pi/4))
-//           in FP32, with the phase (x - pi/4) / (2 pi) = r q - 1/8
-//           revolutions reduced in FP64.
-// The caller passes xf = 2 pi r q, inv = 8 / x and amp = sqrt(2 / (pi x)) in
-// FP32, formed from per-node and per-tap factors so that no division or
-// square root is needed per evaluation.
-__device__ __forceinline__ float j0_fp64phase(double r, double q, float xf, float inv, float amp) {
-    if (xf < 8.0f) return (float)j0_small(kTwoPi * (r * q));
-    float f = (float)hankel_phase_rev(r, q);
-    // hardware sine / cosine of f revolutions (|f| <= 1/2; measured max error
-    // 1.3e-7 on gfx950 against FP64, same order as FP32 rounding of the result)
-    float sn = __builtin_amdgcn_sinf(f);
-    float cs = __builtin_amdgcn_cosf(f);
+//   x >= 8: Hankel form sqrt(2/(pi x)) (P0 cos(x - pi/4) - Q0 sin(x - pi/4)):
+//           the bracket in FP32, with the phase (x - pi/4) / (2 pi) = r q - 1/8
+//           revolutions reduced in FP64, and the amplitude sqrt(2/(pi x)) in
+//           FP64.  The reduced phase is split into an FP32 high part, whose
+//           sine and cosine come from the octant polynomials (about 1 ulp),
+//           and the FP32 rounding of the rest, applied to first order
+//           (sin(a + d) = sin a + d cos a, |d| < 2^-25 revolutions), so that
+//           rounding the phase to FP32 costs nothing.
+// The caller passes xf = 2 pi r q and inv = 8 / x in FP32 and amp in FP64,
+// formed from per-node and per-tap factors so that no division or square
+// root is needed per evaluation.  The kernel values are sums of many such
+// terms that cancel (the chirp oscillates over the nodes), so every rounding
+// step left in FP32 adds to the error in proportion to the sum of |terms|.
+__device__ __forceinline__ double j0_fp64phase(double r, double q, float xf, float inv, double amp) {
+    if (xf < 8.0f) return j0_small(kTwoPi * (r * q));
+    const double f64 = hankel_phase_rev(r, q);
+    const float f = (float)f64;
+    const float d = (float)(kTwoPi * (f64 - (double)f));  // radians
+    float sn0, cs0;
+    sincos_rev(f, &sn0, &cs0);
+    const float sn = fmaf(d, cs0, sn0);
+    const float cs = fmaf(-d, sn0, cs0);
     float t = inv * inv;
     float P = wsp_j0l_p[WSP_J0L_N - 1];
     float Q = wsp_j0l_q[WSP_J0L_N - 1];
@@ -147,7 +156,7 @@ __device__ __forceinline__ float j0_fp64phase(double r, double q, float xf, floa
         Q = fmaf(Q, t, wsp_j0l_q[i]);
     }
     Q *= inv;
-    return amp * (P * cs - Q * sn);
+    return amp * (double)(P * cs - Q * sn);
 }
 
 }  // namespace wsp

@@ -6,17 +6,64 @@
 
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "wsp.h"
 
 namespace wsp {
 
+// Device memory the library allocates for a context (its plan, copies, and
+// the temporaries of planning and building), tracked so that the footprint
+// it reports is exact.  Every allocation of a context's calls goes through
+// dmalloc / dfree while that context's tracker is current on the thread
+// (TrackScope, set by each entry point).
+struct AllocTrack {
+    size_t cur = 0;   // bytes live now
+    size_t peak = 0;  // high-water mark since the last reset
+    std::unordered_map<void *, size_t> live;
+};
+extern thread_local AllocTrack *g_track;
+
+inline hipError_t dmalloc(void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess && g_track && *p) {
+        g_track->live[*p] = bytes;
+        g_track->cur += bytes;
+        if (g_track->cur > g_track->peak) g_track->peak = g_track->cur;
+    }
+    return e;
+}
+template <typename T>
+inline hipError_t dmalloc(T **p, size_t bytes) {
+    return dmalloc(reinterpret_cast<void **>(p), bytes);
+}
+// Frees are best effort (release paths have no caller to report to).
+inline void dfree(void *p) {
+    if (g_track && p) {
+        auto it = g_track->live.find(p);
+        if (it != g_track->live.end()) {
+            g_track->cur -= it->second;
+            g_track->live.erase(it);
+        }
+    }
+    (void)hipFree(p);
+}
+
+struct TrackScope {
+    AllocTrack *prev;
+    explicit TrackScope(AllocTrack *t) : prev(g_track) { g_track = t; }
+    ~TrackScope() { g_track = prev; }
+};
+
 constexpr int kWave = 64;
 constexpr int kTile = 64;          // grid tile side (cells) used for sort keys
 constexpr int kMaxPanels = 1024;   // quadrature panels per visibility (LDS bound)
 constexpr int kProbes = 8;         // probe distances used by the panel error estimate
-constexpr int64_t kItemTaps = 1 << 19; // taps per tile work item (upper bound before the last entry)
+constexpr int64_t kItemTaps = 1 << 19; // default taps per tile work item (bound before the last entry)
+// tile rows per band of the band-major tap layout: 8 or 16, chosen per plan
+// (16 when entries are small, so that a run is most of its entry)
+constexpr int kMaxBandRows = 16;
 
 // Geometry of one operator, all derived once on the host (FP64).
 struct Geom {
@@ -45,6 +92,8 @@ struct Geom {
     double plane_dw, plane_inv_dw;
     // DDE convolution (Eq. (11)): half width h of the per-visibility kernel D
     int dde_h;
+    int64_t item_taps;   // taps per tile work item (before its last entry)
+    int band_rows_param; // requested band height (0: chosen from the plan)
 };
 
 __host__ __device__ inline bool row_used(int V, const Geom &g) {
@@ -130,7 +179,54 @@ struct Plan {
                                   // last usable i | conj << 31, dx0 bits, dy0 bits}; (dx0, dy0) is
                                   // the visibility's offset from the entry's first tap
     float *ptw = nullptr;         // [n_entries] in work-list order: w weight s of the upper plane
+    // Band-major tap layout of the exact kernels.  A run is the part of an
+    // entry that lies in one band (tile_band_rows tile rows): its rows in the band,
+    // row-major.  The tap array holds the work items one after the other; an
+    // item holds its bands in turn, a band (a "unit", item * bands + band)
+    // holds its runs in work-list order.  Runs are numbered twice:
+    // "generation" order groups them by visibility (entries in visibility
+    // order, bands in order), "layout" order follows the tap array.
+    int tile_band_rows = 8;       // tile rows per band (8 or 16)
+    int tile_bands = 8;           // bands per tile, 64 / tile_band_rows
+    int64_t n_runs = 0;
+    int32_t *run_first = nullptr; // [n_entries + 1] first run (generation order) of each entry
+    int64_t *run_tap = nullptr;   // [n_runs] generation order: index of the run's first tap
+    int4 *runrec = nullptr;       // [n_runs] layout order: {first tap relative to its unit,
+                                  // cell0 | nc << 16 | nrows << 24, visibility, generation index}
+                                  // (cell0: band-relative tile cell of the run's first tap)
+    int32_t *unit_run0 = nullptr; // [n_items * bands + 1] first run (layout order) of each unit
+    int64_t *unit_tap0 = nullptr; // [n_items * bands + 1] first tap of each unit
 };
+
+// Position in the tap array of tap (row, col) of sorted visibility p (exact
+// kernels): its entry is the tile of the wrapped footprint it falls in, its
+// run the band of that tile row.
+struct TapLayout {
+    const int64_t *ent_off;
+    const int32_t *run_first;
+    const int64_t *run_tap;
+    int band_rows;
+};
+
+__device__ __forceinline__ int64_t tap_position(const TapLayout &L, int p, int row, int col, int jp,
+                                                int u0w, int v0w) {
+    const int tx0 = u0w / kTile, ty0 = v0w / kTile;
+    const int tvy = (v0w + row) / kTile, tvx = (u0w + col) / kTile;
+    const int ntx = (u0w + jp - 1) / kTile - tx0 + 1;
+    const int64_t e = L.ent_off[p] + (int64_t)(tvy - ty0) * ntx + (tvx - tx0);
+    int r0 = tvy * kTile - v0w;
+    r0 = r0 < 0 ? 0 : r0;
+    int c0 = tvx * kTile - u0w;
+    c0 = c0 < 0 ? 0 : c0;
+    int c1 = (tvx + 1) * kTile - u0w;
+    c1 = c1 > jp ? jp : c1;
+    const int ly = v0w + row - tvy * kTile;   // tile row of the tap
+    const int ly0 = v0w + r0 - tvy * kTile;   // tile row of the entry's first row
+    const int br = L.band_rows;
+    const int b = ly / br, b0 = ly0 / br;
+    const int lo = ly0 > b * br ? ly0 : b * br;  // first tile row of the run
+    return L.run_tap[L.run_first[e] + (b - b0)] + (int64_t)(ly - lo) * (c1 - c0) + (col - c0);
+}
 
 // Stages timed with HIP events when timing is enabled (wsp_set_timing).
 enum Stage { kStTaperPad = 0, kStFftForward, kStDegrid, kStZero, kStGrid, kStFftInverse,
@@ -186,6 +282,9 @@ struct wsp_ctx {
     int64_t quad_panels = 0;
     int64_t quad_capped = 0;
     void *static_scratch = nullptr; // device address of this device's static build workspace
+    wsp::AllocTrack track;          // device memory the library holds for this context
+    size_t plan_peak = 0;           // peak of track.cur during the last planning call
+    size_t build_peak = 0;          // peak above the resident bytes during the last build
     wsp::StageTimer timer;
 };
 
@@ -203,12 +302,15 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
 void free_sorted_plan(Plan &pl);
 
 hipError_t plane_setup(wsp_ctx *c, hipStream_t s);
+hipError_t count_touched_cells(const wsp_ctx *c, int64_t *cells);  // synchronous
+hipError_t find_sorted_index(const wsp_ctx *c, int64_t p, int64_t *sidx);  // synchronous
 
 // build.hip.  ws == nullptr: the build allocates its temporaries; otherwise
 // they are carved from [ws, ws + ws_bytes) and nothing is allocated.
 hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s, void *ws = nullptr,
                         size_t ws_bytes = 0);
 hipError_t launch_plane_build(wsp_ctx *c, hipStream_t s, void *ws = nullptr, size_t ws_bytes = 0);
+size_t build_temp_bytes(const wsp_ctx *c);  // peak temporaries of the allocating build
 int build_batch_in(const wsp_ctx *c, size_t cap);  // batch size whose temporaries fit cap (0: none)
 // the static build workspace of the current device (see build.hip)
 hipError_t static_scratch_init(int device, void **ptr);
@@ -224,5 +326,6 @@ void stage_end(wsp_ctx *c, int stage, hipEvent_t start, hipStream_t s);
 hipError_t run_degrid(wsp_ctx *c, const void *image, void *vis, hipStream_t s, int add_i = 0);
 hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s, int rot = 0);
 hipError_t run_plane_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s);
+hipError_t run_exact_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s);
 
 }  // namespace wsp

@@ -47,8 +47,10 @@ WSP_KERNELS_PLANES = 1
 KERNEL_MODES = {"exact": WSP_KERNELS_EXACT, "planes": WSP_KERNELS_PLANES}
 
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
-            "wsp_set_dde", "wsp_get_stacks", "wsp_get_support", "wsp_footprint", "wsp_bind_memory",
+            "wsp_set_dde", "wsp_get_stacks", "wsp_get_support", "wsp_plan_stats", "wsp_footprint",
+            "wsp_bind_memory",
             "wsp_build_kernels", "wsp_build_kernels_part", "wsp_build_kernels_noalloc", "wsp_quad_stats", "wsp_degrid", "wsp_grid",
+            "wsp_degrid_ws", "wsp_grid_ws",
             "wsp_degrid_pol", "wsp_grid_pol", "wsp_kernel_values", "wsp_set_timing", "wsp_stage_times", "wsp_destroy",
             "wsp_last_error")
 
@@ -77,6 +79,29 @@ class wsp_params(ctypes.Structure):
         ("plane_dq", ctypes.c_double),
         ("plane_dw", ctypes.c_double),
         ("dde_support", ctypes.c_int32),
+        ("item_taps", ctypes.c_int32),
+        ("band_rows", ctypes.c_int32),
+    ]
+
+
+class wsp_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("visibilities", ctypes.c_int64),
+        ("taps", ctypes.c_int64),
+        ("entries", ctypes.c_int64),
+        ("runs", ctypes.c_int64),
+        ("items", ctypes.c_int64),
+        ("tiles", ctypes.c_int64),
+        ("split_tiles", ctypes.c_int64),
+        ("touched_cells", ctypes.c_int64),
+        ("plan_bytes", ctypes.c_int64),
+        ("plan_peak_bytes", ctypes.c_int64),
+        ("build_temp_bytes", ctypes.c_int64),
+        ("last_build_temp_bytes", ctypes.c_int64),
+        ("max_support", ctypes.c_int32),
+        ("kmeans_iterations", ctypes.c_int32),
+        ("band_rows", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -107,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         "wsp_set_dde": (i32, [P, P, P, P]),
         "wsp_get_stacks": (i32, [P, P, P, P]),
         "wsp_get_support": (i32, [P, P, P]),
+        "wsp_plan_stats": (i32, [P, ctypes.POINTER(wsp_plan_info)]),
         "wsp_footprint": (i32, [P, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "wsp_bind_memory": (i32, [P, P, sz, P, sz, P, sz]),
         "wsp_build_kernels": (i32, [P, P]),
@@ -115,6 +141,8 @@ def load_library(path: str = LIB_PATH):
         "wsp_quad_stats": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "wsp_degrid": (i32, [P, P, P, P]),
         "wsp_grid": (i32, [P, P, P, P]),
+        "wsp_degrid_ws": (i32, [P, P, P, P, sz, P, sz, P]),
+        "wsp_grid_ws": (i32, [P, P, P, P, sz, P, sz, P]),
         "wsp_degrid_pol": (i32, [P, P, P, P, P]),
         "wsp_grid_pol": (i32, [P, P, P, P, P]),
         "wsp_kernel_values": (i32, [P, i64, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -194,6 +222,12 @@ def wsp_get_support(ctx, jp: np.ndarray, folded: np.ndarray | None = None):
     _check(load_library().wsp_get_support(ctx, _ptr(jp), _ptr(folded)))
 
 
+def wsp_plan_stats(ctx) -> dict:
+    info = wsp_plan_info()
+    _check(load_library().wsp_plan_stats(ctx, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in info._fields_}
+
+
 def wsp_footprint(ctx):
     k, g, s = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     _check(load_library().wsp_footprint(ctx, ctypes.byref(k), ctypes.byref(g), ctypes.byref(s)))
@@ -230,6 +264,22 @@ def wsp_degrid(ctx, image: torch.Tensor, vis: torch.Tensor, stream=None):
 
 def wsp_grid(ctx, vis: torch.Tensor, image: torch.Tensor, stream=None):
     _check(load_library().wsp_grid(ctx, _ptr(vis), _ptr(image), _stream(stream)))
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def wsp_degrid_ws(ctx, image: torch.Tensor, vis: torch.Tensor, grids: torch.Tensor, scratch: torch.Tensor,
+                  stream=None):
+    _check(load_library().wsp_degrid_ws(ctx, _ptr(image), _ptr(vis), _ptr(grids), _nbytes(grids), _ptr(scratch),
+                                        _nbytes(scratch), _stream(stream)))
+
+
+def wsp_grid_ws(ctx, vis: torch.Tensor, image: torch.Tensor, grids: torch.Tensor, scratch: torch.Tensor,
+                stream=None):
+    _check(load_library().wsp_grid_ws(ctx, _ptr(vis), _ptr(image), _ptr(grids), _nbytes(grids), _ptr(scratch),
+                                      _nbytes(scratch), _stream(stream)))
 
 
 def wsp_degrid_pol(ctx, q_image: torch.Tensor, u_image: torch.Tensor, vis: torch.Tensor, stream=None):
@@ -278,7 +328,7 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
                 max_support: int = 1024, precision: str = "fp32_fp64phase",
                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, device: int = 0,
                 kernels: str = "exact", plane_dq: float = 0.0, plane_dw: float = 0.0,
-                dde_support: int = 0) -> wsp_params:
+                dde_support: int = 0, item_taps: int = 0, band_rows: int = 0) -> wsp_params:
     """Parameters with the library defaults; ``kernels="planes"`` selects taps
     interpolated on the fly from pre-sampled 1-D w-planes (steps plane_dq in
     cells, plane_dw in wavelengths; 0 = the library's defaults 1/64, 1/16)."""
@@ -303,6 +353,8 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
     p.plane_dq = plane_dq
     p.plane_dw = plane_dw
     p.dde_support = dde_support
+    p.item_taps = item_taps
+    p.band_rows = band_rows
     return p
 
 
@@ -384,25 +436,42 @@ class Operator:
     def quad_stats(self):
         return wsp_quad_stats(self.ctx)
 
+    def plan_stats(self) -> dict:
+        return wsp_plan_stats(self.ctx)
+
     def kernel(self, p: int):
         return wsp_kernel_values(self.ctx, p, np.complex128 if self.fp64 else np.complex64)
 
-    def degrid(self, image: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    def new_workspace(self):
+        """A (grids, scratch) pair of this operator's footprint sizes: with one per
+        concurrent request, requests on this operator can run at once on
+        different streams (``workspace=`` of degrid / grid)."""
+        fp = self.footprint
+        return (torch.empty(max(fp["grid_bytes"], 256), dtype=torch.uint8, device=self.device),
+                torch.empty(max(fp["scratch_bytes"], 256), dtype=torch.uint8, device=self.device))
+
+    def degrid(self, image: torch.Tensor, out: torch.Tensor | None = None, stream=None, workspace=None):
         image = image.to(self.device, self.real_dtype).contiguous()
         if image.shape != (self.n, self.n):
             raise ValueError(f"image must be {self.n}x{self.n}")
         if out is None:
             out = torch.empty(self.m, dtype=self.complex_dtype, device=self.device)
-        wsp_degrid(self.ctx, image, out, stream)
+        if workspace is None:
+            wsp_degrid(self.ctx, image, out, stream)
+        else:
+            wsp_degrid_ws(self.ctx, image, out, workspace[0], workspace[1], stream)
         return out
 
-    def grid(self, vis: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    def grid(self, vis: torch.Tensor, out: torch.Tensor | None = None, stream=None, workspace=None):
         vis = vis.to(self.device, self.complex_dtype).contiguous()
         if vis.shape != (self.m,):
             raise ValueError(f"vis must have {self.m} entries")
         if out is None:
             out = torch.empty((self.n, self.n), dtype=self.real_dtype, device=self.device)
-        wsp_grid(self.ctx, vis, out, stream)
+        if workspace is None:
+            wsp_grid(self.ctx, vis, out, stream)
+        else:
+            wsp_grid_ws(self.ctx, vis, out, workspace[0], workspace[1], stream)
         return out
 
     def degrid_pol(self, q_image: torch.Tensor, u_image: torch.Tensor, out: torch.Tensor | None = None,

@@ -38,6 +38,7 @@ def test_default_params():
     ("quad_max_panels", 4), ("quad_max_panels", 5000), ("precision", 7), ("kmeans_max_iter", 0),
     ("max_support", 2), ("kernel_mode", 7), ("plane_dq", -1.0), ("plane_dq", 2.0),
     ("plane_dw", float("nan")), ("dde_support", 2), ("dde_support", 17), ("dde_support", -1),
+    ("item_taps", -1), ("item_taps", (1 << 24) + 1), ("band_rows", 4), ("band_rows", 32),
 ])
 def test_create_rejects_invalid_parameters(field, value):
     p = wsp.make_params(64, math.radians(10.0))
@@ -62,26 +63,28 @@ def test_dde_needs_stored_kernels():
     assert ei.value.status == wsp.WSP_EINVAL
 
 
-def test_params_layout_matches_header(tmp_path):
-    """ctypes mirror of wsp_params has the C struct's size and field offsets."""
+@pytest.mark.parametrize("struct", [wsp.wsp_params, wsp.wsp_plan_info])
+def test_struct_layout_matches_header(tmp_path, struct):
+    """ctypes mirrors of the ABI structs have the C structs' sizes and field offsets."""
     import ctypes
     import shutil
     import subprocess
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    fields = [f for f, _ in wsp.wsp_params._fields_]
+    name = struct.__name__
+    fields = [f for f, _ in struct._fields_]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"wsp.h\"\nint main(void){\n"
-                   "printf(\"%zu\\n\", sizeof(wsp_params));\n" +
-                   "".join(f"printf(\"%zu\\n\", offsetof(wsp_params, {f}));\n" for f in fields) +
+                   f"printf(\"%zu\\n\", sizeof({name}));\n" +
+                   "".join(f"printf(\"%zu\\n\", offsetof({name}, {f}));\n" for f in fields) +
                    "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
-    assert out[0] == ctypes.sizeof(wsp.wsp_params)
-    assert out[1:] == [getattr(wsp.wsp_params, f).offset for f in fields]
+    assert out[0] == ctypes.sizeof(struct)
+    assert out[1:] == [getattr(struct, f).offset for f in fields]
 
 
 def test_grid_side_must_tile():
