@@ -212,3 +212,27 @@ def test_delta_dde_is_the_plain_operator():
         assert np.linalg.norm(y - y_plain) <= 1e-5 * np.linalg.norm(y_plain)
     finally:
         a.close()
+
+
+def test_forced_quadrature_cap_warns_and_completes():
+    """A panel cap far below what wide w needs: the build stops refining, returns
+    WSP_WARN_QUAD_MAXEVAL with the count of capped visibilities, and still exits
+    normally with every tap and output finite."""
+    uvw = np.array([[10.0, 5.0, 400.0], [3.0, -2.0, 350.0], [-7.0, 4.0, -300.0], [1.0, 1.0, 0.0]])
+    params = wsp.make_params(256, math.radians(25.0), quad_max_panels=8, max_support=512)
+    op = wsp.Operator(params, uvw, build=False)
+    with pytest.warns(UserWarning, match="quadrature tolerance"):
+        status = op.build()
+    assert status == wsp.WSP_WARN_QUAD_MAXEVAL
+    panels, capped = op.quad_stats()
+    print(f"capped {capped} of {op.m}, panels {panels}", flush=True)
+    assert 3 <= capped <= op.m and panels <= 8 * op.m
+    for p in range(op.m):
+        assert np.isfinite(op.kernel(p)[0]).all()
+    y = op.degrid(torch.from_numpy(syn.point_source_sky(256, 10, "exp", 3))).cpu().numpy()
+    assert np.isfinite(y).all()
+    # the default cap meets the tolerance on the same visibilities
+    full = wsp.Operator(wsp.make_params(256, math.radians(25.0), max_support=512), uvw)
+    assert full.build_status == wsp.WSP_OK and full.quad_stats()[1] == 0
+    op.close()
+    full.close()

@@ -3,8 +3,7 @@
 On a 32^2 problem the GPU (all-FP64 path) and the oracle drive the same
 loop; the operators agree to the kernels' quadrature tolerance, so ||Phi||^2
 and the FISTA iterates agree to ~1e-6.  On the 2048^2, 5e6-visibility,
-8-stack workload a few FISTA iterations must lower the objective (by 27% in
-8 iterations when measured).
+8-stack workload the FP32 loop follows the all-FP64 loop iterate by iterate.
 """
 import math
 import time
@@ -86,28 +85,39 @@ def test_admm_matches_oracle():
         gpu.close()
 
 
-def test_fista_lowers_objective_8_stacks():
+def test_fista_8_stacks_fp32_follows_fp64():
+    """FISTA on the 2048^2, 5e6-visibility, 8-stack workload: the FP32 loop
+    follows the all-FP64 loop (whose operator is pinned to the oracle by the
+    parity tests) iterate by iterate, to FP32 accuracy, and keeps x >= 0."""
     wl = syn.WORKLOADS["mwa_2048_8_stacks"]
     uvw = syn.workload_uvw(wl)
-    params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
-                             precision=wl.precision)
-    op = wsp.Operator(params, uvw)
-    try:
-        sky = torch.from_numpy(syn.workload_sky(wl)).cuda().float()
-        y = op.degrid(sky)
-        L = imaging.power_norm2(op, n_iter=20)
-        lam = 1e-3 * float(torch.max(torch.abs(op.grid(y))))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = imaging.fista_l1(op, y, lam, n_iter=8, norm2=L)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 8
-        print(f"FISTA: {dt * 1e3:.1f} ms per iteration (with objective), objective {res.objective[0]:.4e} -> "
-              f"{res.objective[-1]:.4e}", flush=True)
-        # deconvolving a 2048^2 dirty image converges slowly; after 8 iterations
-        # the objective has dropped by a good fraction and is at its lowest
-        assert res.objective[-1] < 0.8 * res.objective[0]
-        assert res.objective[-1] == min(res.objective)
-        assert float(res.x.min()) >= 0.0
-    finally:
-        op.close()
+    runs = {}
+    labels = centres = None
+    for precision in ("fp64", "fp32_fp64phase"):
+        params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
+                                 precision=precision)
+        op = wsp.Operator(params, uvw, labels=labels, centres=centres)
+        if labels is None:
+            labels, centres, _ = op.stacks()
+        try:
+            sky = torch.from_numpy(syn.workload_sky(wl)).cuda().to(op.real_dtype)
+            y = op.degrid(sky)
+            if precision == "fp64":
+                L = imaging.power_norm2(op, n_iter=20)
+                lam = 1e-3 * float(torch.max(torch.abs(op.grid(y))))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = imaging.fista_l1(op, y, lam, n_iter=8, norm2=L)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 8
+            runs[precision] = (res.x.double().cpu().numpy(), res.objective)
+            print(f"{precision} FISTA: {dt * 1e3:.1f} ms per iteration (with objective), objective "
+                  f"{res.objective[0]:.6e} -> {res.objective[-1]:.6e}", flush=True)
+            assert float(res.x.min()) >= 0.0
+        finally:
+            op.close()
+    (x64, o64), (x32, o32) = runs["fp64"], runs["fp32_fp64phase"]
+    err = float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64))
+    print(f"FP32 vs FP64 iterate after 8 iterations: {err:.2e}", flush=True)
+    assert err <= 1e-4
+    assert max(abs(a - b) / abs(b) for a, b in zip(o32, o64)) <= 1e-4
