@@ -57,6 +57,8 @@ def parse():
                     help="exact per-visibility taps, or taps interpolated from 1-D w-planes")
     ap.add_argument("--band-rows", type=int, default=0, choices=[0, 8, 16],
                     help="exact mode: tile rows per band of the tap layout (0: the library's choice)")
+    ap.add_argument("--tap-layout", default="auto", choices=["auto", "runs", "interleaved"],
+                    help="exact mode: tap layout (auto: interleaved when runs are short)")
     ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving", "build"],
                     help="operator: the metric; copy: a plain 2 GiB device copy used to "
                          "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE readings; serving: "
@@ -457,7 +459,7 @@ def build_rate(args):
 
 
 def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_override=None,
-                 want_y: bool = False, band_rows: int = 0):
+                 want_y: bool = False, band_rows: int = 0, tap_layout: str = "auto"):
     """Plan, build and time `steps` operator steps of one workload; returns a dict."""
     import torch
 
@@ -474,7 +476,8 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
     cb = 16 if fp64 else 8
     planes = kernels == "planes"
     params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
-                             precision=precision, kernels=kernels, band_rows=band_rows)
+                             precision=precision, kernels=kernels, band_rows=band_rows,
+                             tap_layout=tap_layout)
     t0 = time.perf_counter()
     op = wsp.Operator(params, uvw, build=False)
     torch.cuda.synchronize()
@@ -516,8 +519,9 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
 
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     dom = "degrid" if per_launch["degrid"] >= per_launch["grid"] else "grid"
-    stage_kernels = {"degrid": "k_degrid_runs + k_degrid_reduce_runs",
-                     "grid": "k_prep_vis + k_grid_runs + k_reduce_tiles"}
+    lanes = int(st["tap_layout"]) == 2
+    stage_kernels = {"degrid": ("k_degrid_lanes" if lanes else "k_degrid_runs") + " + k_degrid_reduce_runs",
+                     "grid": "k_prep_vis + " + ("k_grid_lanes" if lanes else "k_grid_runs") + " + k_reduce_tiles"}
     if planes:
         flops = PLANE_FLOPS_PER_TAP * taps
         achieved_t = flops / (per_launch[dom] * 1e-3) / 1e12
@@ -553,6 +557,8 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
                   "kernel_bytes": op.footprint["kernel_bytes"], "taps": taps,
                   "mean_jp": math.sqrt(taps / m), "max_jp": int(st["max_support"]),
                   "entries": int(st["entries"]), "runs": int(st["runs"]), "band_rows": int(st["band_rows"]),
+                  "tap_layout": {1: "runs", 2: "interleaved"}.get(int(st["tap_layout"]), "planes"),
+                  "lanes_busy": (taps / (64 * int(st["group_steps"])) if int(st["group_steps"]) else None),
                   "items": int(st["items"]),
                   "tiles": int(st["tiles"]), "split_tiles": int(st["split_tiles"]),
                   "touched_cells": int(st["touched_cells"]), "plan_bytes": int(st["plan_bytes"]),
@@ -588,7 +594,7 @@ def main():
     wl = syn.WORKLOADS[args.workload]
     precision = args.precision or wl.precision
     head = run_operator(wl, precision, args.kernels, args.steps, args.warmup, args.m_vis, want_y=True,
-                        band_rows=args.band_rows)
+                        band_rows=args.band_rows, tap_layout=args.tap_layout)
     uvw = head.pop("_uvw")
     planes = args.kernels == "planes"
     result = {

@@ -62,6 +62,11 @@ typedef int32_t wsp_status;
 #define WSP_KERNELS_EXACT 0       /* one set of J_p x J_p taps per visibility (Eq. (6))   */
 #define WSP_KERNELS_PLANES 1      /* taps interpolated on the fly from 1-D w-planes     */
 
+#define WSP_LAYOUT_AUTO 0         /* exact mode: the library's choice (contiguous runs)  */
+#define WSP_LAYOUT_RUNS 1         /* each run's taps contiguous, row-major               */
+#define WSP_LAYOUT_INTERLEAVED 2  /* runs of a band in groups of 64, tap k of every run
+                                     of a group stored together                          */
+
 typedef struct wsp_params {
     int32_t n;              /* image side N, even, multiple of 32                       */
     double oversample;      /* alpha; alpha*N must be an integer multiple of 64         */
@@ -87,9 +92,9 @@ typedef struct wsp_params {
     int32_t item_taps;      /* taps per tile work item before its last entry; 0: 2^19 (a
                                tuning and test knob: small values split tiles over items) */
     int32_t band_rows;      /* exact mode: tile rows per band of the tap layout, 8 or 16;
-                               0 chooses from the plan (16 when the mean taps per
-                               (visibility, tile) overlap is below 160). Results do
-                               not depend on it beyond rounding order               */
+                               0 selects 8. Results do not depend on it beyond
+                               rounding order (a tuning and test knob)              */
+    int32_t tap_layout;     /* exact mode: WSP_LAYOUT_* (see "Tap layouts" below)        */
 } wsp_params;
 
 /* Direction-dependent effects (Sec. 5.2, Eq. (11)).  With dde_support = J_D
@@ -126,6 +131,23 @@ typedef struct wsp_params {
  * mode.  Only with precision WSP_FP32_FP64PHASE.  The interpolation error with
  * the default steps is about 1e-4 of the kernel peak on 25-degree fields
  * (bilinear error ~ dq^2/8 max|d2K/dq2| + dw^2/8 max|d2K/dw2|). */
+
+/* Tap layouts (exact mode).  The taps of every visibility are cut by the 64 x
+ * 64 grid tiles they fall in and by bands of band_rows tile rows; a "run" is
+ * the part of one visibility's footprint in one band of one tile, row-major.
+ * The kernel buffer holds the tile work items one after the other, and an
+ * item its bands in turn.  Within a band:
+ *   WSP_LAYOUT_RUNS: the runs one after the other, each contiguous;
+ *   WSP_LAYOUT_INTERLEAVED: the runs sorted by length (longest first), in
+ *     groups of 64; a group stores tap 0 of each of its runs, then tap 1 of
+ *     each run still that long, and so on, so that one wavefront reads a
+ *     group with one lane per run and contiguous loads.
+ * The interleaved layout makes degrid faster on short runs (no lane looks for
+ * the run its tap belongs to) but its grid adds with LDS atomics, and runs of
+ * a step collide on cells, which makes it slow; WSP_LAYOUT_AUTO takes
+ * contiguous runs.  The layout changes where taps are stored, not their
+ * values; results differ only in rounding order.  wsp_kernel_values reads
+ * any layout. */
 
 typedef struct wsp_ctx wsp_ctx;
 
@@ -201,7 +223,9 @@ typedef struct wsp_plan_info {
     int32_t max_support;      /* largest J_p                                              */
     int32_t kmeans_iterations;/* Algorithm 1 iterations (0 after wsp_set_stacks)          */
     int32_t band_rows;        /* tile rows per band of the exact tap layout (0 in w-plane mode) */
-    int32_t reserved;         /* 0                                                        */
+    int32_t tap_layout;       /* WSP_LAYOUT_RUNS or WSP_LAYOUT_INTERLEAVED (0 in w-plane mode) */
+    int64_t group_steps;      /* interleaved layout: sum over groups of their longest run
+                                 (taps / (64 group_steps) is the share of busy lanes) */
 } wsp_plan_info;
 
 /* Fill *info.  touched_cells is counted on the device (synchronises it).

@@ -294,6 +294,8 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
         return fail(WSP_EINVAL, "item_taps must be in [0, 2^24] (0 = default)");
     if (p.band_rows != 0 && p.band_rows != 8 && p.band_rows != 16)
         return fail(WSP_EINVAL, "band_rows must be 0, 8 or 16");
+    if (p.tap_layout < WSP_LAYOUT_AUTO || p.tap_layout > WSP_LAYOUT_INTERLEAVED)
+        return fail(WSP_EINVAL, "tap_layout must be WSP_LAYOUT_AUTO, _RUNS or _INTERLEAVED");
     if (!(p.plane_dq >= 0.0) || !(p.plane_dw >= 0.0) || !std::isfinite(p.plane_dq) ||
         !std::isfinite(p.plane_dw) || p.plane_dq > 1.0)
         return fail(WSP_EINVAL, "plane_dq must be in [0, 1] and plane_dw >= 0 (0 = default)");
@@ -325,6 +327,7 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     g.dde_h = p.dde_support > 1 ? (p.dde_support - 1) / 2 : 0;
     g.item_taps = p.item_taps > 0 ? (int64_t)p.item_taps : kItemTaps;
     g.band_rows_param = p.band_rows;
+    g.tap_layout_param = p.tap_layout;
     double xr = 2.0 * M_PI * g.a * g.r_max;
     double ymax = std::fmax(0.25 * g.beta * g.beta, std::fabs(0.25 * (g.beta * g.beta - xr * xr)));
     int terms = (int)std::ceil(2.0 * std::sqrt(ymax)) + 30;
@@ -551,7 +554,8 @@ wsp_status wsp_plan_stats(wsp_ctx *c, wsp_plan_info *info) {
     info->max_support = pl.max_jp;
     info->kmeans_iterations = c->iterations;
     info->band_rows = c->g.planes ? 0 : pl.tile_band_rows;
-    info->reserved = 0;
+    info->tap_layout = c->g.planes ? 0 : (pl.interleaved ? WSP_LAYOUT_INTERLEAVED : WSP_LAYOUT_RUNS);
+    info->group_steps = pl.interleaved ? pl.group_steps : 0;
     return WSP_OK;
 }
 

@@ -1200,6 +1200,159 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_runs(const typename Typ
     for (int r = 0; r < kBR; ++r) dst[(int64_t)r * ld + lane] = sb[r * kTile + lane];
 }
 
+// ---- exact kernels on the interleaved tap layout -------------------------
+// Short runs (many w-stacks, supports of a few cells): one wavefront per unit
+// as above, but lane i serves run i of each group of 64 of the unit's runs
+// (longest first).  Step k of a group reads tap k of every run at least k + 1
+// long, a contiguous range of the tap array, so every load instruction is
+// coalesced and no lane ever looks for the run a tap belongs to.  A lane
+// walks its run's cells row by row within the band.  kLaneSteps steps' loads
+// are issued before their taps are used.
+constexpr int kLaneSteps = 8;
+
+// GC_k, W_k (degrid): each lane's run partial goes to dpart at the run's
+// generation index; k_degrid_reduce_runs sums them per visibility.
+template <bool kFP64, int kBR>
+__global__ __launch_bounds__(64 * kRunWaves) void k_degrid_lanes(const typename Types<kFP64>::C *__restrict__ taps,
+                                                                 const typename Types<kFP64>::C *__restrict__ grids,
+                                                                 typename Types<kFP64>::C *dpart, RunArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    __shared__ C s_band[kRunWaves][kBR * kTile];
+    const int wid = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
+    if (u >= a.n_units) return;  // uniform over the wavefront
+    const int r_beg = a.unit_run0[u], r_end = a.unit_run0[u + 1];
+    if (r_beg >= r_end) return;
+    constexpr int kNB = kTile / kBR;
+    const int item = (int)(u / kNB), band = (int)(u % kNB);
+    C *sb = s_band[wid];
+    {
+        const C *src = tile_origin(grids, a.item_key[item], a.tile_bits, a.G) + (int64_t)band * kBR * a.G;
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
+    }
+    wave_fence();
+    const C *tp = taps + a.unit_tap0[u];
+    for (int g0 = r_beg; g0 < r_end; g0 += 64) {
+        const int4 rec = a.runrec[g0 + lane];
+        const int nc = (rec.y >> 16) & 255;
+        const int len = nc * ((rec.y >> 24) & 255);
+        const int lmax = __builtin_amdgcn_readfirstlane(len);  // lane 0 holds the longest run
+        const C *gp = tp + __builtin_amdgcn_readfirstlane(rec.x);
+        int cell = rec.y & 0xFFFF, col = 0;
+        int S = 0;  // taps of the group stored before the current step
+        R ar = 0, ai = 0;
+        for (int k0 = 0; k0 < lmax; k0 += kLaneSteps) {
+            C K[kLaneSteps];
+#pragma unroll
+            for (int j = 0; j < kLaneSteps; ++j) {
+                const bool on = k0 + j < len;
+                K[j].x = 0;
+                K[j].y = 0;
+                if (on) K[j] = load_tap(gp + S + lane);
+                S += (int)__popcll(__ballot(on));
+            }
+#pragma unroll
+            for (int j = 0; j < kLaneSteps; ++j) {
+                const C z = sb[k0 + j < len ? cell : 0];  // K = 0 past the run's end
+                ar += K[j].x * z.x - K[j].y * z.y;
+                ai += K[j].x * z.y + K[j].y * z.x;
+                ++col;
+                ++cell;
+                if (col == nc) {
+                    col = 0;
+                    cell += kTile - nc;
+                }
+            }
+        }
+        if (rec.w >= 0) {
+            C o;
+            o.x = ar;
+            o.y = ai;
+            dpart[rec.w] = o;
+        }
+    }
+}
+
+// GC_k^dagger (grid): each lane adds conj(K) y of its run into the band in
+// LDS with LDS atomic adds (runs of a step may share cells); the band is then
+// stored as in k_grid_runs.
+template <bool kFP64, int kBR>
+__global__ __launch_bounds__(64 * kRunWaves) void k_grid_lanes(const typename Types<kFP64>::C *__restrict__ taps,
+                                                               const typename Types<kFP64>::C *__restrict__ yw,
+                                                               typename Types<kFP64>::C *grids, RunArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    __shared__ C s_band[kRunWaves][kBR * kTile];
+    const int wid = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
+    if (u >= a.n_units) return;  // uniform over the wavefront
+    const int r_beg = a.unit_run0[u], r_end = a.unit_run0[u + 1];
+    constexpr int kNB = kTile / kBR;
+    const int item = (int)(u / kNB), band = (int)(u % kNB);
+    const bool sole = a.item_sole[item] != 0;
+    if (sole && r_beg >= r_end) return;  // nothing to add to a band the zero pass cleared
+    C *sb = s_band[wid];
+    C zero;
+    zero.x = 0;
+    zero.y = 0;
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = zero;
+    wave_fence();
+    const C *tp = taps + a.unit_tap0[u];
+    for (int g0 = r_beg; g0 < r_end; g0 += 64) {
+        const int4 rec = a.runrec[g0 + lane];
+        const int nc = (rec.y >> 16) & 255;
+        const int len = nc * ((rec.y >> 24) & 255);
+        const int lmax = __builtin_amdgcn_readfirstlane(len);
+        const C *gp = tp + __builtin_amdgcn_readfirstlane(rec.x);
+        const C y = rec.w >= 0 ? yw[rec.z] : zero;
+        int cell = rec.y & 0xFFFF, col = 0;
+        int S = 0;
+        for (int k0 = 0; k0 < lmax; k0 += kLaneSteps) {
+            C K[kLaneSteps];
+#pragma unroll
+            for (int j = 0; j < kLaneSteps; ++j) {
+                const bool on = k0 + j < len;
+                K[j].x = 0;
+                K[j].y = 0;
+                if (on) K[j] = load_tap(gp + S + lane);
+                S += (int)__popcll(__ballot(on));
+            }
+#pragma unroll
+            for (int j = 0; j < kLaneSteps; ++j) {
+                if (k0 + j < len) {
+                    atomicAdd(&sb[cell].x, K[j].x * y.x + K[j].y * y.y);  // conj(K) y
+                    atomicAdd(&sb[cell].y, K[j].x * y.y - K[j].y * y.x);
+                }
+                ++col;
+                ++cell;
+                if (col == nc) {
+                    col = 0;
+                    cell += kTile - nc;
+                }
+            }
+        }
+    }
+    const uint32_t key = a.item_key[item];
+    C *dst;
+    int64_t ld;
+    if (sole) {
+        dst = tile_origin(grids, key, a.tile_bits, a.G);
+        ld = a.G;
+    } else {
+        dst = (C *)a.partial + (int64_t)a.item_slot[item] * kTile * kTile;
+        ld = kTile;
+    }
+    dst += (int64_t)band * kBR * ld;
+    wave_fence();
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) dst[(int64_t)r * ld + lane] = sb[r * kTile + lane];
+}
+
 // Sum the partial tiles of each tile shared by several items, in the order of
 // the tile's items (deterministic), and store the result in the grid.
 template <bool kFP64>
@@ -1392,7 +1545,10 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
             // group width from the mean run length
             const int64_t mean_run = pl.n_runs > 0 ? pl.total_taps / pl.n_runs : 1;
             const dim3 gd(blocks(ra.n_units, kRunWaves)), bd(64 * kRunWaves);
-            if (pl.tile_band_rows == 16) {
+            if (pl.interleaved) {
+                if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_lanes<kFP64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
+                else hipLaunchKernelGGL((k_degrid_lanes<kFP64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
+            } else if (pl.tile_band_rows == 16) {
                 if (mean_run < 48) hipLaunchKernelGGL((k_degrid_runs<kFP64, 8, 16>), gd, bd, 0, s, tp, gr, dp, ra);
                 else if (mean_run < 192) hipLaunchKernelGGL((k_degrid_runs<kFP64, 16, 16>), gd, bd, 0, s, tp, gr, dp, ra);
                 else hipLaunchKernelGGL((k_degrid_runs<kFP64, 64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
@@ -1449,10 +1605,14 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     if (!g.planes) {
         const RunArgs ra = run_args(c);
         const dim3 gd(blocks(ra.n_units, kRunWaves)), bd(64 * kRunWaves);
-        if (ra.n_units > 0 && pl.tile_band_rows == 16)
+        if (ra.n_units > 0 && pl.interleaved) {
+            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_lanes<kFP64, 16>), gd, bd, 0, s, tp, yw, gr, ra);
+            else hipLaunchKernelGGL((k_grid_lanes<kFP64, 8>), gd, bd, 0, s, tp, yw, gr, ra);
+        } else if (ra.n_units > 0 && pl.tile_band_rows == 16) {
             hipLaunchKernelGGL((k_grid_runs<kFP64, 16>), gd, bd, 0, s, tp, yw, gr, ra);
-        else if (ra.n_units > 0)
+        } else if (ra.n_units > 0) {
             hipLaunchKernelGGL((k_grid_runs<kFP64, 8>), gd, bd, 0, s, tp, yw, gr, ra);
+        }
     } else if constexpr (!kFP64) {  // w-plane kernels (FP32 path only)
         if (pl.n_items > 0) {
             const unsigned nb = (unsigned)(8 * ((pl.n_items + 7) / 8));
@@ -1495,7 +1655,7 @@ hipError_t run_grid(wsp_ctx *c, const void *vis, void *image, hipStream_t s, int
 
 hipError_t run_exact_taps(wsp_ctx *c, int64_t sidx, void *out_dev, hipStream_t s) {
     const Plan &pl = c->plan;
-    const TapLayout lay{pl.ent_off, pl.run_first, pl.run_tap, pl.tile_band_rows};
+    const TapLayout lay = tap_layout(pl);
     if (c->p.precision == WSP_FP64)
         hipLaunchKernelGGL(k_vis_taps<double2>, dim3(64), dim3(256), 0, s, (const double2 *)c->taps, lay, pl.jp,
                            pl.u0w, pl.v0w, sidx, (double2 *)out_dev);

@@ -212,12 +212,31 @@ __device__ float eval_panel_probes(double a, double b, double weff, double qstep
     return (float)err;
 }
 
+// Sum over each row of 16 lanes with DPP moves (no LDS): quad swaps, then the
+// half-row and row mirrors; every lane of the row ends with the row's sum.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), kCtrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return v;
+}
+
 // The same G7/K15 estimates for the marked panels idx[0 .. ne), one
 // Gauss-Kronrod node per lane: 16-lane groups (15 nodes used) take 4 panels
-// per pass and sum their nodes with shuffles.  Used when a round has few
+// per pass and sum their nodes across the group.  Used when a round has few
 // panels to evaluate, where one panel per lane would leave most lanes idle.
-// Panel idx[k]'s error goes to errv[idx[k]]; with acc the K15 values are
-// added into sre / sim of the group's first lane.
+// The estimate needs only K15 - G7, one sum per probe; the K15 values
+// themselves only when acc (the first round).  Panel idx[k]'s error goes to
+// errv[idx[k]]; with acc the K15 values are added into sre / sim of the
+// group's first lane.
 __device__ void eval_marked_grouped(const float *cur, const int *idx, int ne, double weff, double qstep,
                                     const Geom &g, float *errv, double *sre, double *sim, bool acc,
                                     int lane) {
@@ -232,48 +251,43 @@ __device__ void eval_marked_grouped(const float *cur, const int *idx, int ne, do
             b = (double)fabsf(cur[pi + 1]);
         }
         const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
-        double kr[kProbes], ki[kProbes], gr[kProbes], gi[kProbes];
+        double tr[kProbes], ti[kProbes];
+        double wk = 0.0, wg = 0.0;
 #pragma unroll
-        for (int j = 0; j < kProbes; ++j) kr[j] = ki[j] = gr[j] = gi[j] = 0.0;
+        for (int j = 0; j < kProbes; ++j) tr[j] = ti[j] = 0.0;
         if (k < ne && nd < WSP_GK_N) {
             const double r = fma(half, wsp_gk_x[nd], mid);
             double are, aim;
             node_value(r, weff, g, &are, &aim);
-            const double wk = wsp_gk_wk[nd], wg = wsp_gk_wg[nd];
+            wk = wsp_gk_wk[nd];
+            wg = wsp_gk_wg[nd];
 #pragma unroll
             for (int j = 0; j < kProbes; ++j) {
                 const double q = qstep * j;
                 const double x = kTwoPi * (r * q);
                 const double J = x < 8.0 ? j0_small(x) : j0_fp64(r, q, 8.0 / x, sqrt(0.6366197723675814 / x));
-                const double tr = are * J, ti = aim * J;
-                kr[j] = wk * tr;
-                ki[j] = wk * ti;
-                gr[j] = wg * tr;
-                gi[j] = wg * ti;
+                tr[j] = are * J;
+                ti[j] = aim * J;
             }
         }
+        const double wd = wk - wg;
+        double err = 0.0;
 #pragma unroll
         for (int j = 0; j < kProbes; ++j) {
-            for (int o = 8; o > 0; o >>= 1) {  // within the 16-lane group
-                kr[j] += __shfl_xor(kr[j], o, 64);
-                ki[j] += __shfl_xor(ki[j], o, 64);
-                gr[j] += __shfl_xor(gr[j], o, 64);
-                gi[j] += __shfl_xor(gi[j], o, 64);
-            }
+            const double dr = row_sum16(wd * tr[j]), di = row_sum16(wd * ti[j]);
+            err = fmax(err, half * sqrt(dr * dr + di * di));
         }
-        if (k < ne && nd == 0) {
-            double err = 0.0;
+        if (acc) {
 #pragma unroll
             for (int j = 0; j < kProbes; ++j) {
-                const double dr = kr[j] - gr[j], di = ki[j] - gi[j];
-                err = fmax(err, half * sqrt(dr * dr + di * di));
-                if (acc) {
-                    sre[j] += half * kr[j];
-                    sim[j] += half * ki[j];
+                const double kr = row_sum16(wk * tr[j]), ki = row_sum16(wk * ti[j]);
+                if (k < ne && nd == 0) {
+                    sre[j] += half * kr;
+                    sim[j] += half * ki;
                 }
             }
-            errv[pi] = (float)err;
         }
+        if (k < ne && nd == 0) errv[pi] = (float)err;
     }
 }
 
@@ -986,7 +1000,7 @@ hipError_t launch_build(wsp_ctx *c, int64_t first, int64_t count, hipStream_t s,
     A.u0w = pl.u0w;
     A.v0w = pl.v0w;
     A.tap_off = pl.tap_off;
-    A.lay = TapLayout{pl.ent_off, pl.run_first, pl.run_tap, pl.tile_band_rows};
+    A.lay = tap_layout(pl);
     A.taps = c->taps;
     A.dde_u = c->dde_u;
     A.dde_v = c->dde_v;

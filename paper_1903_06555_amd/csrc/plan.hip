@@ -12,9 +12,6 @@
 
 namespace wsp {
 
-// mean taps per entry below which a plan uses bands of 16 rows
-constexpr int64_t kSmallEntryTapsPlan = 160;
-
 namespace {
 
 #define WSP_TRY(expr)                         \
@@ -426,10 +423,11 @@ __global__ void k_item_marks(const int32_t *__restrict__ item_start, int n_items
     if (i >= 1 && i < n_items) marks[item_start[i]] = 1;
 }
 
-// Runs in generation order: sort key (item, band, work position) and tap count.
+// Runs in generation order: sort key (item, band, longest first), tap count
+// and entry.  Equal keys keep generation order (the radix sort is stable).
 __global__ void k_run_keys(const int4 *__restrict__ ent, const int32_t *__restrict__ run_first,
                            const int32_t *__restrict__ pos_of, const int32_t *__restrict__ item_of_pos,
-                           int64_t E, int br, uint64_t *key, int32_t *gidx, int32_t *rlen) {
+                           int64_t E, int br, uint64_t *key, int32_t *gidx, int32_t *rlen, int32_t *rent) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int z = ent[e].z;
@@ -443,14 +441,16 @@ __global__ void k_run_keys(const int4 *__restrict__ ent, const int32_t *__restri
         const int g = run_first[e] + k;
         const int lo = ly0 > b * br ? ly0 : b * br;
         const int hi = (ly0 + nr < (b + 1) * br) ? ly0 + nr : (b + 1) * br;
-        key[g] = (it << 35) | ((uint64_t)b << 31) | (uint64_t)(uint32_t)s;
+        const int len = (hi - lo) * nc;  // <= 16 * 64
+        key[g] = (it << 15) | ((uint64_t)b << 11) | (uint64_t)(2047 - len);
         gidx[g] = g;
-        rlen[g] = (hi - lo) * nc;
+        rlen[g] = len;
+        rent[g] = (int32_t)e;
     }
 }
 
 __device__ __forceinline__ int64_t run_unit(uint64_t key, int bands) {
-    return (int64_t)(key >> 35) * bands + (int64_t)((key >> 31) & 15);
+    return (int64_t)(key >> 15) * bands + (int64_t)((key >> 11) & 15);
 }
 
 __global__ void k_run_lengths(const int32_t *__restrict__ lay2gen, const int32_t *__restrict__ rlen,
@@ -484,22 +484,94 @@ __global__ void k_unit_taps(const int32_t *__restrict__ unit_run0, const int64_t
     if (u <= U) unit_tap0[u] = start_lay[unit_run0[u]];
 }
 
-__global__ void k_run_records(const uint64_t *__restrict__ keys, const int32_t *__restrict__ lay2gen,
-                              const int64_t *__restrict__ start_lay, const int64_t *__restrict__ unit_tap0,
-                              const int32_t *__restrict__ ent_sorted, const int4 *__restrict__ ent, int64_t R,
-                              int br, int4 *runrec) {
-    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (L >= R) return;
-    const uint64_t key = keys[L];
-    const int b = (int)((key >> 31) & 15);
-    const int4 en = ent[ent_sorted[(int64_t)(key & 0x7FFFFFFFull)]];
+// Record of the run in layout position L, stored at slot[L] (or L).
+__device__ __forceinline__ int4 run_record(uint64_t key, const int4 &en, int br, int rel, int gen) {
+    const int b = (int)((key >> 11) & 15);
     const int z = en.z;
     const int nc = z & 255, nr = (z >> 8) & 255, lx0 = (z >> 16) & 255, ly0 = (z >> 24) & 255;
     const int lo = ly0 > b * br ? ly0 : b * br;
     const int hi = (ly0 + nr < (b + 1) * br) ? ly0 + nr : (b + 1) * br;
     const int cell0 = (lo - b * br) * kTile + lx0;
-    runrec[L] = make_int4((int)(start_lay[L] - unit_tap0[run_unit(key, kTile / br)]),
-                          cell0 | (nc << 16) | ((hi - lo) << 24), en.x, lay2gen[L]);
+    return make_int4(rel, cell0 | (nc << 16) | ((hi - lo) << 24), en.x, gen);
+}
+
+__global__ void k_run_records(const uint64_t *__restrict__ keys, const int32_t *__restrict__ lay2gen,
+                              const int64_t *__restrict__ start_lay, const int64_t *__restrict__ unit_tap0,
+                              const int32_t *__restrict__ rent, const int4 *__restrict__ ent, int64_t R,
+                              int br, int4 *runrec) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= R) return;
+    const uint64_t key = keys[L];
+    const int g = lay2gen[L];
+    runrec[L] = run_record(key, ent[rent[g]], br, (int)(start_lay[L] - unit_tap0[run_unit(key, kTile / br)]), g);
+}
+
+// ---- interleaved variant: units padded to whole groups of 64 runs
+__global__ void k_padded_counts(const int32_t *__restrict__ unit_run0, int64_t U, int64_t *cnt) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > U) return;
+    cnt[u] = u == U ? 0 : ((unit_run0[u + 1] - unit_run0[u] + 63) & ~63);
+}
+
+// Slot of sorted run L, its length and record (.x set by k_group_bases);
+// the unit of each group's first slot.
+__global__ void k_pad_scatter(const uint64_t *__restrict__ keys, const int32_t *__restrict__ lay2gen,
+                              const int32_t *__restrict__ unit_run0, const int64_t *__restrict__ pad0,
+                              const int32_t *__restrict__ rlen, const int32_t *__restrict__ rent,
+                              const int4 *__restrict__ ent, int64_t R, int br, int32_t *run_lay,
+                              uint16_t *len16, int4 *runrec, int32_t *grp_unit) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= R) return;
+    const uint64_t key = keys[L];
+    const int64_t u = run_unit(key, kTile / br);
+    const int64_t slot = pad0[u] + (L - unit_run0[u]);
+    const int g = lay2gen[L];
+    run_lay[g] = (int32_t)slot;
+    len16[slot] = (uint16_t)rlen[g];
+    runrec[slot] = run_record(key, ent[rent[g]], br, 0, g);
+    if ((slot & 63) == 0) grp_unit[slot >> 6] = (int32_t)u;
+}
+
+// Per group: suffix sums of the lengths, the group's taps and its longest run
+// (slot 0: lengths are sorted longest first).
+__global__ void k_group_sums(const uint16_t *__restrict__ len16, int64_t n_groups, uint32_t *suf,
+                             int64_t *grp_len, unsigned long long *steps) {
+    int64_t G = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (G > n_groups) return;
+    if (G == n_groups) {
+        grp_len[G] = 0;
+        return;
+    }
+    uint32_t acc = 0;
+    for (int j = 63; j >= 0; --j) {
+        acc += len16[G * 64 + j];
+        suf[G * 64 + j] = acc;
+    }
+    grp_len[G] = acc;
+    atomicAdd(steps, (unsigned long long)len16[G * 64]);
+}
+
+__global__ void k_unit_taps_padded(const int64_t *__restrict__ pad0, const int64_t *__restrict__ grp_tap,
+                                   int64_t U, int64_t *unit_tap0, int32_t *unit_run0) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > U) return;
+    unit_tap0[u] = grp_tap[pad0[u] >> 6];
+    unit_run0[u] = (int32_t)pad0[u];  // units now start at their padded slots
+}
+
+// .x of every slot of group G: the group's first tap relative to its unit
+// (slot 0 of a group always holds a run: a unit's runs fill its first slots).
+__global__ void k_group_bases(const int64_t *__restrict__ grp_tap, const int64_t *__restrict__ unit_tap0,
+                              const int32_t *__restrict__ grp_unit, int64_t n_groups, int4 *runrec) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_groups * 64) return;
+    const int64_t G = t >> 6;
+    runrec[t].x = (int)(grp_tap[G] - unit_tap0[grp_unit[G]]);
+}
+
+__global__ void k_fill_padding(int64_t n, int4 *runrec) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) runrec[t] = make_int4(0, 0, 0, -1);
 }
 
 // Touched cells: every row of an entry covers columns lx0 .. lx0 + nc - 1 of
@@ -651,12 +723,16 @@ void free_sorted_plan(Plan &pl) {
     pl.ptw = nullptr;
     pl.n_pairs = 0;
     pl.table_len = 0;
-    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec, pl.unit_run0, pl.unit_tap0};
+    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec, pl.unit_run0, pl.unit_tap0,
+                     pl.run_lay,   pl.len16,   pl.suf,    pl.grp_tap};
     for (void *q : rptrs) dfree(q);
-    pl.run_first = pl.unit_run0 = nullptr;
-    pl.run_tap = pl.unit_tap0 = nullptr;
+    pl.run_first = pl.unit_run0 = pl.run_lay = nullptr;
+    pl.run_tap = pl.unit_tap0 = pl.grp_tap = nullptr;
     pl.runrec = nullptr;
-    pl.n_runs = 0;
+    pl.len16 = nullptr;
+    pl.suf = nullptr;
+    pl.n_runs = pl.n_runs_padded = pl.group_steps = 0;
+    pl.interleaved = false;
 }
 
 // ---- w-plane mode ---------------------------------------------------------------
@@ -987,20 +1063,106 @@ static hipError_t make_entries(Plan &pl, const Geom &g, int tile_bits, hipStream
 #undef WSP_ESTEP
 }
 
+// The interleaved tap layout (see Plan) from the runs in sorted order:
+// units padded to whole groups, groups' tap offsets and suffix sums, records.
+static hipError_t make_interleaved(Plan &pl, int64_t R, int64_t U, const uint64_t *key_sorted,
+                                   const int32_t *lay2gen, const int32_t *rlen, const int32_t *rent,
+                                   hipStream_t s) {
+    int64_t *cnt = nullptr, *pad0 = nullptr, *grp_len = nullptr;
+    int32_t *grp_unit = nullptr;
+    unsigned long long *steps = nullptr;
+    void *tmp = nullptr;
+    size_t need = 0;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        void *ptrs[] = {cnt, pad0, grp_len, grp_unit, steps, tmp};
+        for (void *q : ptrs) dfree(q);
+    };
+#define WSP_ISTEP(expr)        \
+    do {                       \
+        e = (expr);            \
+        if (e != hipSuccess) { \
+            cleanup();         \
+            return e;          \
+        }                      \
+    } while (0)
+    WSP_ISTEP(dalloc(&cnt, U + 1));
+    WSP_ISTEP(dalloc(&pad0, U + 1));
+    hipLaunchKernelGGL(k_padded_counts, dim3(grid1d(U + 1, 256)), dim3(256), 0, s, pl.unit_run0, U, cnt);
+    WSP_ISTEP(hipGetLastError());
+    WSP_ISTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, need, cnt, pad0, (int)(U + 1), s));
+    WSP_ISTEP(dmalloc(&tmp, need ? need : 1));
+    WSP_ISTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need, cnt, pad0, (int)(U + 1), s));
+    int64_t Rp = 0;
+    WSP_ISTEP(hipMemcpyAsync(&Rp, pad0 + U, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    WSP_ISTEP(hipStreamSynchronize(s));
+    if (Rp >= 0x7FFFFFC0LL) {  // slots are int32
+        cleanup();
+        return hipErrorInvalidValue;
+    }
+    const int64_t n_groups = Rp / 64;
+    pl.n_runs_padded = Rp;
+    WSP_ISTEP(dalloc(&pl.runrec, Rp));
+    WSP_ISTEP(dalloc(&pl.len16, Rp));
+    WSP_ISTEP(dalloc(&pl.suf, Rp));
+    WSP_ISTEP(dalloc(&pl.run_lay, R));
+    WSP_ISTEP(dalloc(&pl.grp_tap, n_groups + 1));
+    WSP_ISTEP(dalloc(&grp_unit, n_groups));
+    WSP_ISTEP(dalloc(&grp_len, n_groups + 1));
+    WSP_ISTEP(dalloc(&steps, 1));
+    if (Rp > 0) hipLaunchKernelGGL(k_fill_padding, dim3(grid1d(Rp, 256)), dim3(256), 0, s, Rp, pl.runrec);
+    WSP_ISTEP(hipMemsetAsync(pl.len16, 0, sizeof(uint16_t) * (size_t)Rp, s));
+    WSP_ISTEP(hipMemsetAsync(steps, 0, sizeof(unsigned long long), s));
+    if (R > 0) {
+        hipLaunchKernelGGL(k_pad_scatter, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, lay2gen, pl.unit_run0,
+                           pad0, rlen, rent, pl.ent, R, pl.tile_band_rows, pl.run_lay, pl.len16, pl.runrec,
+                           grp_unit);
+    }
+    hipLaunchKernelGGL(k_group_sums, dim3(grid1d(n_groups + 1, 256)), dim3(256), 0, s, pl.len16, n_groups,
+                       pl.suf, grp_len, steps);
+    WSP_ISTEP(hipGetLastError());
+    size_t need2 = 0;
+    WSP_ISTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, grp_len, pl.grp_tap, (int)(n_groups + 1), s));
+    if (need2 > need) {
+        dfree(tmp);
+        tmp = nullptr;
+        WSP_ISTEP(dmalloc(&tmp, need2));
+    }
+    WSP_ISTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need2, grp_len, pl.grp_tap, (int)(n_groups + 1), s));
+    hipLaunchKernelGGL(k_unit_taps_padded, dim3(grid1d(U + 1, 256)), dim3(256), 0, s, pad0, pl.grp_tap, U,
+                       pl.unit_tap0, pl.unit_run0);
+    if (n_groups > 0) {
+        hipLaunchKernelGGL(k_group_bases, dim3(grid1d(n_groups * 64, 256)), dim3(256), 0, s, pl.grp_tap,
+                           pl.unit_tap0, grp_unit, n_groups, pl.runrec);
+    }
+    WSP_ISTEP(hipGetLastError());
+    int64_t total = 0;
+    unsigned long long st = 0;
+    WSP_ISTEP(hipMemcpyAsync(&total, pl.grp_tap + n_groups, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    WSP_ISTEP(hipMemcpyAsync(&st, steps, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    WSP_ISTEP(hipStreamSynchronize(s));  // before the temporaries are released
+    pl.group_steps = (int64_t)st;
+    cleanup();
+    return total == pl.total_taps ? hipSuccess : hipErrorUnknown;  // every tap in exactly one run
+#undef WSP_ISTEP
+}
+
 // Runs and the band-major tap layout (see Plan), after the work lists.
 static hipError_t make_runs(Plan &pl, hipStream_t s) {
     const int64_t E = pl.n_entries;
     const int br = pl.tile_band_rows;
     const int64_t U = (int64_t)pl.n_items * pl.tile_bands;
     int32_t *pos_of = nullptr, *marks = nullptr, *item_of_pos = nullptr, *gidx = nullptr,
-            *lay2gen = nullptr, *rlen = nullptr;
+            *lay2gen = nullptr, *rlen = nullptr, *rent = nullptr, *pad_cnt = nullptr, *grp_unit = nullptr;
     uint64_t *key = nullptr, *key_sorted = nullptr;
-    int64_t *len_lay = nullptr, *start_lay = nullptr;
+    int64_t *len_lay = nullptr, *start_lay = nullptr, *grp_len = nullptr;
+    unsigned long long *steps = nullptr;
     void *tmp = nullptr;
     size_t tmp_bytes = 0;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
-        void *ptrs[] = {pos_of, marks, item_of_pos, gidx, lay2gen, rlen, key, key_sorted, len_lay, start_lay, tmp};
+        void *ptrs[] = {pos_of, marks,   item_of_pos, gidx,     lay2gen, rlen, rent,  pad_cnt,
+                        grp_unit, key, key_sorted, len_lay, start_lay, grp_len, steps, tmp};
         for (void *q : ptrs) dfree(q);
     };
 #define WSP_RSTEP(expr)        \
@@ -1034,6 +1196,8 @@ static hipError_t make_runs(Plan &pl, hipStream_t s) {
     WSP_RSTEP(hipStreamSynchronize(s));
     const int64_t R = R32;
     pl.n_runs = R;
+    pl.n_runs_padded = R;
+    pl.group_steps = 0;
     // work position of each entry, item of each work position
     WSP_RSTEP(dalloc(&pos_of, E));
     WSP_RSTEP(dalloc(&item_of_pos, E));
@@ -1052,17 +1216,38 @@ static hipError_t make_runs(Plan &pl, hipStream_t s) {
     WSP_RSTEP(dalloc(&gidx, R));
     WSP_RSTEP(dalloc(&lay2gen, R));
     WSP_RSTEP(dalloc(&rlen, R));
+    WSP_RSTEP(dalloc(&rent, R));
     hipLaunchKernelGGL(k_run_keys, dim3(grid1d(E, 256)), dim3(256), 0, s, pl.ent, pl.run_first, pos_of,
-                       item_of_pos, E, br, key, gidx, rlen);
+                       item_of_pos, E, br, key, gidx, rlen, rent);
     WSP_RSTEP(hipGetLastError());
     int item_bits = 1;
     while (((int64_t)1 << item_bits) < (int64_t)pl.n_items) ++item_bits;
+    if (15 + item_bits > 64) {
+        cleanup();
+        return hipErrorInvalidValue;
+    }
     need = 0;
     WSP_RSTEP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key, key_sorted, gidx, lay2gen, (int)R, 0,
-                                                 35 + item_bits, s));
+                                                 15 + item_bits, s));
     WSP_RSTEP(scratch(need));
     WSP_RSTEP(hipcub::DeviceRadixSort::SortPairs(tmp, need, key, key_sorted, gidx, lay2gen, (int)R, 0,
-                                                 35 + item_bits, s));
+                                                 15 + item_bits, s));
+    // units (runs in unpadded layout order)
+    WSP_RSTEP(dalloc(&pl.unit_run0, U + 1));
+    WSP_RSTEP(dalloc(&pl.unit_tap0, U + 1));
+    if (R > 0) {
+        hipLaunchKernelGGL(k_unit_heads, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, R, U, pl.tile_bands,
+                           pl.unit_run0);
+    } else {
+        WSP_RSTEP(hipMemsetAsync(pl.unit_run0, 0, sizeof(int32_t) * (size_t)(U + 1), s));
+    }
+    WSP_RSTEP(hipGetLastError());
+    pl.interleaved = pl.layout_param == WSP_LAYOUT_INTERLEAVED;
+    if (pl.interleaved) {
+        e = make_interleaved(pl, R, U, key_sorted, lay2gen, rlen, rent, s);
+        cleanup();
+        return e;
+    }
     // tap offsets in layout order
     WSP_RSTEP(dalloc(&len_lay, R + 1));
     WSP_RSTEP(dalloc(&start_lay, R + 1));
@@ -1074,20 +1259,11 @@ static hipError_t make_runs(Plan &pl, hipStream_t s) {
     WSP_RSTEP(scratch(need));
     WSP_RSTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need, len_lay, start_lay, (int)(R + 1), s));
     hipLaunchKernelGGL(k_run_taps, dim3(grid1d(R, 256)), dim3(256), 0, s, lay2gen, start_lay, R, pl.run_tap);
-    // units
-    WSP_RSTEP(dalloc(&pl.unit_run0, U + 1));
-    WSP_RSTEP(dalloc(&pl.unit_tap0, U + 1));
-    if (R > 0) {
-        hipLaunchKernelGGL(k_unit_heads, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, R, U, pl.tile_bands,
-                           pl.unit_run0);
-    } else {
-        WSP_RSTEP(hipMemsetAsync(pl.unit_run0, 0, sizeof(int32_t) * (size_t)(U + 1), s));
-    }
     hipLaunchKernelGGL(k_unit_taps, dim3(grid1d(U + 1, 256)), dim3(256), 0, s, pl.unit_run0, start_lay, U,
                        pl.unit_tap0);
     WSP_RSTEP(dalloc(&pl.runrec, R));
     hipLaunchKernelGGL(k_run_records, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, lay2gen, start_lay,
-                       pl.unit_tap0, pl.ent_sorted, pl.ent, R, br, pl.runrec);
+                       pl.unit_tap0, rent, pl.ent, R, br, pl.runrec);
     WSP_RSTEP(hipGetLastError());
     int64_t total = 0;
     WSP_RSTEP(hipMemcpyAsync(&total, start_lay + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1248,11 +1424,11 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     }
     hipError_t e3 = make_entries(pl, g, tile_bits, s);
     if (e3 != hipSuccess || g.planes) return e3;
-    // bands of 16 rows when entries are small (a few stacks' worth of taps),
-    // so that a run holds most of its entry; 8 rows otherwise
-    pl.tile_band_rows = g.band_rows_param > 0 ? g.band_rows_param
-                                              : (pl.total_taps < kSmallEntryTapsPlan * pl.n_entries ? 16 : 8);
+    // bands of 8 rows unless asked otherwise (16-row bands halve the run
+    // kernels' occupancy, which costs more than the longer runs gain)
+    pl.tile_band_rows = g.band_rows_param > 0 ? g.band_rows_param : 8;
     pl.tile_bands = kTile / pl.tile_band_rows;
+    pl.layout_param = g.tap_layout_param;
     if (pl.n_entries >= 0x7FFFFFF0LL / pl.tile_bands) return hipErrorInvalidValue;  // run indices are int32
     return make_runs(pl, s);
 #undef WSP_STEP

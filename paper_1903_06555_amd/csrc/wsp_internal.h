@@ -94,6 +94,7 @@ struct Geom {
     int dde_h;
     int64_t item_taps;   // taps per tile work item (before its last entry)
     int band_rows_param; // requested band height (0: chosen from the plan)
+    int tap_layout_param; // requested tap layout (WSP_LAYOUT_*)
 };
 
 __host__ __device__ inline bool row_used(int V, const Geom &g) {
@@ -188,11 +189,26 @@ struct Plan {
     // order, bands in order), "layout" order follows the tap array.
     int tile_band_rows = 8;       // tile rows per band (8 or 16)
     int tile_bands = 8;           // bands per tile, 64 / tile_band_rows
+    // Interleaved variant (short runs): a band's runs are sorted by length,
+    // longest first, and padded with empty runs to a multiple of 64; each group
+    // of 64 stores tap k of its runs (those longer than k) together, k = 0, 1,
+    // ..., so tap k of the run in lane i of group G sits at
+    // grp_tap[G] + sum_j min(len_j, k) + i.
+    bool interleaved = false;
+    int layout_param = 0;         // requested layout (WSP_LAYOUT_*)
+    int64_t n_runs_padded = 0;    // layout slots (interleaved: multiple of 64 per unit)
+    int64_t group_steps = 0;      // sum over groups of their longest run
+    int32_t *run_lay = nullptr;   // [n_runs] generation order: layout slot of the run
+    uint16_t *len16 = nullptr;    // [n_runs_padded] layout order: run length (0 = padding)
+    uint32_t *suf = nullptr;      // [n_runs_padded] layout order: sum of len over the group from here on
+    int64_t *grp_tap = nullptr;   // [n_runs_padded / 64 + 1] first tap of each group
     int64_t n_runs = 0;
     int32_t *run_first = nullptr; // [n_entries + 1] first run (generation order) of each entry
     int64_t *run_tap = nullptr;   // [n_runs] generation order: index of the run's first tap
-    int4 *runrec = nullptr;       // [n_runs] layout order: {first tap relative to its unit,
-                                  // cell0 | nc << 16 | nrows << 24, visibility, generation index}
+                                  // (contiguous runs only)
+    int4 *runrec = nullptr;       // [n_runs_padded] layout order: {first tap of the run (of its
+                                  // group, interleaved) relative to its unit, cell0 | nc << 16 |
+                                  // nrows << 24, visibility, generation index (-1: padding)}
                                   // (cell0: band-relative tile cell of the run's first tap)
     int32_t *unit_run0 = nullptr; // [n_items * bands + 1] first run (layout order) of each unit
     int64_t *unit_tap0 = nullptr; // [n_items * bands + 1] first tap of each unit
@@ -204,9 +220,36 @@ struct Plan {
 struct TapLayout {
     const int64_t *ent_off;
     const int32_t *run_first;
-    const int64_t *run_tap;
+    const int64_t *run_tap;   // contiguous runs
+    const int32_t *run_lay;   // interleaved: slot of each run, and its group's data
+    const uint16_t *len16;
+    const uint32_t *suf;
+    const int64_t *grp_tap;
     int band_rows;
+    bool interleaved;
 };
+
+inline TapLayout tap_layout(const Plan &pl) {
+    return TapLayout{pl.ent_off, pl.run_first, pl.run_tap, pl.run_lay, pl.len16,
+                     pl.suf,     pl.grp_tap,   pl.tile_band_rows, pl.interleaved};
+}
+
+// Taps stored before tap k of the run in lane i of an interleaved group: the
+// runs of the group at least k long (a prefix, lengths descending) hold k
+// taps each before step k, the others all theirs, plus the i runs of lanes
+// before i at step k.
+__device__ __forceinline__ int64_t interleaved_position(const TapLayout &L, int64_t slot, int k) {
+    const int64_t g0 = slot & ~(int64_t)63;
+    const int lane = (int)(slot & 63);
+    int lo = 0, hi = 64;  // t = number of runs with length >= k
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)L.len16[g0 + mid] >= k) lo = mid + 1;
+        else hi = mid;
+    }
+    const int64_t rest = lo < 64 ? (int64_t)L.suf[g0 + lo] : 0;
+    return L.grp_tap[g0 >> 6] + (int64_t)k * lo + rest + lane;
+}
 
 __device__ __forceinline__ int64_t tap_position(const TapLayout &L, int p, int row, int col, int jp,
                                                 int u0w, int v0w) {
@@ -225,7 +268,10 @@ __device__ __forceinline__ int64_t tap_position(const TapLayout &L, int p, int r
     const int br = L.band_rows;
     const int b = ly / br, b0 = ly0 / br;
     const int lo = ly0 > b * br ? ly0 : b * br;  // first tile row of the run
-    return L.run_tap[L.run_first[e] + (b - b0)] + (int64_t)(ly - lo) * (c1 - c0) + (col - c0);
+    const int k = (ly - lo) * (c1 - c0) + (col - c0);  // tap of the run
+    const int64_t run = L.run_first[e] + (b - b0);
+    if (L.interleaved) return interleaved_position(L, L.run_lay[run], k);
+    return L.run_tap[run] + k;
 }
 
 // Stages timed with HIP events when timing is enabled (wsp_set_timing).

@@ -45,6 +45,10 @@ PRECISIONS = {"fp32_fp64phase": WSP_FP32_FP64PHASE, "fp64": WSP_FP64}
 WSP_KERNELS_EXACT = 0
 WSP_KERNELS_PLANES = 1
 KERNEL_MODES = {"exact": WSP_KERNELS_EXACT, "planes": WSP_KERNELS_PLANES}
+WSP_LAYOUT_AUTO = 0
+WSP_LAYOUT_RUNS = 1
+WSP_LAYOUT_INTERLEAVED = 2
+TAP_LAYOUTS = {"auto": WSP_LAYOUT_AUTO, "runs": WSP_LAYOUT_RUNS, "interleaved": WSP_LAYOUT_INTERLEAVED}
 
 EXPORTED = ("wsp_default_params", "wsp_create", "wsp_set_uvw", "wsp_set_stacks",
             "wsp_set_dde", "wsp_get_stacks", "wsp_get_support", "wsp_plan_stats", "wsp_footprint",
@@ -81,6 +85,7 @@ class wsp_params(ctypes.Structure):
         ("dde_support", ctypes.c_int32),
         ("item_taps", ctypes.c_int32),
         ("band_rows", ctypes.c_int32),
+        ("tap_layout", ctypes.c_int32),
     ]
 
 
@@ -101,7 +106,8 @@ class wsp_plan_info(ctypes.Structure):
         ("max_support", ctypes.c_int32),
         ("kmeans_iterations", ctypes.c_int32),
         ("band_rows", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tap_layout", ctypes.c_int32),
+        ("group_steps", ctypes.c_int64),
     ]
 
 
@@ -328,7 +334,8 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
                 max_support: int = 1024, precision: str = "fp32_fp64phase",
                 kmeans_tol: float = 1e-3, kmeans_max_iter: int = 100, device: int = 0,
                 kernels: str = "exact", plane_dq: float = 0.0, plane_dw: float = 0.0,
-                dde_support: int = 0, item_taps: int = 0, band_rows: int = 0) -> wsp_params:
+                dde_support: int = 0, item_taps: int = 0, band_rows: int = 0,
+                tap_layout: str = "auto") -> wsp_params:
     """Parameters with the library defaults; ``kernels="planes"`` selects taps
     interpolated on the fly from pre-sampled 1-D w-planes (steps plane_dq in
     cells, plane_dw in wavelengths; 0 = the library's defaults 1/64, 1/16)."""
@@ -355,6 +362,7 @@ def make_params(n: int, fov_rad: float, *, oversample: float = 2.0, kb_support: 
     p.dde_support = dde_support
     p.item_taps = item_taps
     p.band_rows = band_rows
+    p.tap_layout = TAP_LAYOUTS[tap_layout]
     return p
 
 

@@ -39,6 +39,7 @@ def test_default_params():
     ("max_support", 2), ("kernel_mode", 7), ("plane_dq", -1.0), ("plane_dq", 2.0),
     ("plane_dw", float("nan")), ("dde_support", 2), ("dde_support", 17), ("dde_support", -1),
     ("item_taps", -1), ("item_taps", (1 << 24) + 1), ("band_rows", 4), ("band_rows", 32),
+    ("tap_layout", -1), ("tap_layout", 3),
 ])
 def test_create_rejects_invalid_parameters(field, value):
     p = wsp.make_params(64, math.radians(10.0))

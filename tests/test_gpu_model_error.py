@@ -66,7 +66,7 @@ def workload(request):
 
 def _degrid(wl, fov, uvw, labels, centres, sky, f):
     params = wsp.make_params(wl.n, fov, n_stacks=wl.n_stacks, fold=wl.fold, precision=wl.precision,
-                             support_scale=f)
+                             support_scale=f, max_support=8192)
     op = wsp.Operator(params, uvw, labels=labels, centres=centres)
     try:
         assert op.build_status == wsp.WSP_OK

@@ -16,6 +16,12 @@ wide-field problems whose grid tiles are split over many work items.
   hundreds of runs and the grid kernel stages its run records in many
   chunks.
 
+Both tap layouts run on every problem: runs stored one after the other
+("runs") and runs of a band interleaved in groups of 64 ("interleaved", one
+lane per run); their taps must be bit-identical (the layout only moves
+them), and repeated calls bit-identical (the interleaved grid adds with LDS
+atomics).
+
 Bars, per element: max_p |dy_p| / max|y| and max |dx| / max|x| <= 1e-5 on
 the FP32 path (the degrid tolerance of the benchmark spec, applied to every
 visibility rather than to the norm) and <= 1e-7 on the FP64 path (the FP64
@@ -75,10 +81,14 @@ def problem(request):
     return _CACHE[request.param]
 
 
-def _op(pb, precision, item_taps):
+LAYOUTS = ["runs", "interleaved"]
+
+
+def _op(pb, precision, item_taps, layout="auto"):
     ref = pb["ref"]
     _, _, _, k, fold, _, _ = PROBLEMS[pb["name"]]
-    params = wsp.make_params(N, FOV, n_stacks=k, fold=fold, precision=precision, item_taps=item_taps)
+    params = wsp.make_params(N, FOV, n_stacks=k, fold=fold, precision=precision, item_taps=item_taps,
+                             tap_layout=layout)
     return wsp.Operator(params, pb["uvw"], weights=pb["wts"], labels=ref.labels, centres=ref.centres)
 
 
@@ -86,14 +96,19 @@ def _max_rel(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_fp64phase"])
-def test_every_visibility_and_pixel(problem, precision):
+def test_every_visibility_and_pixel(problem, precision, layout):
     ref = problem["ref"]
     for item_taps in PROBLEMS[problem["name"]][6]:
-        op = _op(problem, precision, item_taps)
+        op = _op(problem, precision, item_taps, layout)
         st = op.plan_stats()
-        print(f"{problem['name']} {precision} item_taps={item_taps}: {st['items']} items, {st['tiles']} tiles, "
-              f"{st['split_tiles']} split, {st['entries']} entries, {st['runs']} runs", flush=True)
+        print(f"{problem['name']} {precision} {layout} item_taps={item_taps}: {st['items']} items, "
+              f"{st['tiles']} tiles, {st['split_tiles']} split, {st['entries']} entries, {st['runs']} runs, "
+              f"group steps {st['group_steps']}", flush=True)
+        assert st["tap_layout"] == wsp.TAP_LAYOUTS[layout]
+        if layout == "interleaved":
+            assert st["taps"] <= 64 * st["group_steps"]
         if item_taps:
             assert st["split_tiles"] >= 8 and st["items"] >= 3 * st["tiles"]
         else:
@@ -104,6 +119,8 @@ def test_every_visibility_and_pixel(problem, precision):
         y = op.degrid(torch.from_numpy(problem["x"])).cpu().numpy()
         op.scratch.fill_(255)
         xa = op.grid(torch.from_numpy(problem["y_in"])).cpu().numpy()
+        assert np.array_equal(xa, op.grid(torch.from_numpy(problem["y_in"])).cpu().numpy())
+        assert np.array_equal(y, op.degrid(torch.from_numpy(problem["x"])).cpu().numpy())
         ey, ex = _max_rel(y, problem["y_ref"]), _max_rel(xa, problem["x_ref"])
         worst = int(np.argmax(np.abs(y - problem["y_ref"])))
         print(f"  degrid max|dy|/max|y| {ey:.2e} (worst vis {worst}, J_p {ref.jp[worst]}), "
@@ -115,16 +132,19 @@ def test_every_visibility_and_pixel(problem, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_fp64phase"])
 def test_every_tap(problem, precision):
     ref = problem["ref"]
-    op = _op(problem, precision, PROBLEMS[problem["name"]][6][0])
+    ops = {lay: _op(problem, precision, PROBLEMS[problem["name"]][6][0], lay) for lay in LAYOUTS}
     worst = 0.0
     for p in range(ref.m):
-        Kg, u0, v0 = op.kernel(p)
+        Kg, u0, v0 = ops["runs"].kernel(p)
+        Ki, ui, vi = ops["interleaved"].kernel(p)
+        assert (ui, vi) == (u0, v0) and np.array_equal(Ki, Kg)  # same values, other places
         ru0, rv0, Kr = ref.kernel(p)
         assert (u0, v0) == (ru0, rv0) and Kg.shape == Kr.shape
         worst = max(worst, float(np.max(np.abs(Kg - Kr)) / np.max(np.abs(Kr))))
     print(f"{problem['name']} {precision}: worst tap error {worst:.2e}", flush=True)
     assert worst <= 1e-6
-    op.close()
+    for op in ops.values():
+        op.close()
 
 
 def test_adjoint_identity_fp64_split(problem):
