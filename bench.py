@@ -520,8 +520,11 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     dom = "degrid" if per_launch["degrid"] >= per_launch["grid"] else "grid"
     lanes = int(st["tap_layout"]) == 2
-    stage_kernels = {"degrid": ("k_degrid_lanes" if lanes else "k_degrid_runs") + " + k_degrid_reduce_runs",
-                     "grid": "k_prep_vis + " + ("k_grid_lanes" if lanes else "k_grid_runs") + " + k_reduce_tiles"}
+    grid_runs = 2 * int(st["long_taps"]) > taps
+    stage_kernels = {"degrid": ("k_degrid_lanes" if lanes else "k_degrid_class") + " + k_degrid_reduce_runs",
+                     "grid": "k_prep_vis + " + ("k_grid_lanes" if lanes else
+                                                "k_grid_runs" if grid_runs else "k_prep_runs + k_grid_class")
+                             + " + k_reduce_tiles"}
     if planes:
         flops = PLANE_FLOPS_PER_TAP * taps
         achieved_t = flops / (per_launch[dom] * 1e-3) / 1e12
@@ -555,10 +558,11 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
                    **({"kernels": "planes", "plane_dq": 1 / 64, "plane_dw": 1 / 16} if planes else {})},
         "setup": {"plan_s": t_plan, "build_s": t_build, "build_mvis_per_s": m / t_build / 1e6,
                   "kernel_bytes": op.footprint["kernel_bytes"], "taps": taps,
-                  "mean_jp": math.sqrt(taps / m), "max_jp": int(st["max_support"]),
+                  "rms_jp": math.sqrt(taps / m), "max_jp": int(st["max_support"]),
                   "entries": int(st["entries"]), "runs": int(st["runs"]), "band_rows": int(st["band_rows"]),
                   "tap_layout": {1: "runs", 2: "interleaved"}.get(int(st["tap_layout"]), "planes"),
                   "lanes_busy": (taps / (64 * int(st["group_steps"])) if int(st["group_steps"]) else None),
+                  "classes": int(st["classes"]), "long_taps": int(st["long_taps"]),
                   "items": int(st["items"]),
                   "tiles": int(st["tiles"]), "split_tiles": int(st["split_tiles"]),
                   "touched_cells": int(st["touched_cells"]), "plan_bytes": int(st["plan_bytes"]),

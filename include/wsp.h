@@ -226,6 +226,11 @@ typedef struct wsp_plan_info {
     int32_t tap_layout;       /* WSP_LAYOUT_RUNS or WSP_LAYOUT_INTERLEAVED (0 in w-plane mode) */
     int64_t group_steps;      /* interleaved layout: sum over groups of their longest run
                                  (taps / (64 group_steps) is the share of busy lanes) */
+    int64_t classes;          /* contiguous runs: classes of neighbouring runs of one shape
+                                 (same width, rows and first cell) within a band   */
+    int64_t long_taps;        /* taps in classes whose shape has more than 64 taps (when
+                                 more than half the taps, grid streams runs instead
+                                 of accumulating classes in registers)              */
 } wsp_plan_info;
 
 /* Fill *info.  touched_cells is counted on the device (synchronises it).

@@ -556,6 +556,8 @@ wsp_status wsp_plan_stats(wsp_ctx *c, wsp_plan_info *info) {
     info->band_rows = c->g.planes ? 0 : pl.tile_band_rows;
     info->tap_layout = c->g.planes ? 0 : (pl.interleaved ? WSP_LAYOUT_INTERLEAVED : WSP_LAYOUT_RUNS);
     info->group_steps = pl.interleaved ? pl.group_steps : 0;
+    info->classes = pl.n_classes;
+    info->long_taps = pl.long_taps;
     return WSP_OK;
 }
 

@@ -947,6 +947,8 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
 // unit's band of the tile in LDS; the wavefronts of a block are independent
 // (no block barriers), so a block only groups them for the LDS allocation.
 struct RunArgs {
+    const int4 *clsrec;
+    const int32_t *unit_cls0;
     const int4 *runrec;
     const int32_t *unit_run0;
     const int64_t *unit_tap0;
@@ -974,95 +976,22 @@ __device__ __forceinline__ int bits_upto(uint64_t m, int lane) {
     return below + (int)((m >> lane) & 1ull);
 }
 
-// GC_k, W_k (degrid) on runs: a wavefront stages its unit's band of the FFT
-// grid, then groups of kG lanes take one run each (64 / kG consecutive runs
-// per pass), multiply its taps by the staged grid values and reduce; the
-// run's partial sum goes to dpart at the run's generation index (runs of a
-// visibility are consecutive there), summed per visibility by
-// k_degrid_reduce_runs.  kG follows the mean run length (short runs: narrow
-// groups, so a pass covers more runs and keeps more loads in flight); the
-// next pass's run records are loaded before this pass's taps are consumed.
-template <bool kFP64, int kG, int kBR>
-__global__ __launch_bounds__(64 * kRunWaves) void k_degrid_runs(const typename Types<kFP64>::C *__restrict__ taps,
-                                                                const typename Types<kFP64>::C *__restrict__ grids,
-                                                                typename Types<kFP64>::C *dpart, RunArgs a) {
-    using R = typename Types<kFP64>::R;
-    using C = typename Types<kFP64>::C;
-    constexpr int kPer = 64 / kG;               // runs per pass
-    constexpr int kU = kG >= 64 ? 8 : 512 / (kG * 8) > 8 ? 8 : 512 / (kG * 8);  // load slots per lane
-    __shared__ C s_band[kRunWaves][kBR * kTile];
-    const int wid = wave_index();
-    const int lane = threadIdx.x & 63;
-    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
-    if (u >= a.n_units) return;  // uniform over the wavefront
-    const int r_beg = a.unit_run0[u], r_end = a.unit_run0[u + 1];
-    if (r_beg >= r_end) return;
-    constexpr int kNB = kTile / kBR;
-    const int item = (int)(u / kNB), band = (int)(u % kNB);
-    C *sb = s_band[wid];
-    {
-        const C *src = tile_origin(grids, a.item_key[item], a.tile_bits, a.G) + (int64_t)band * kBR * a.G;
-#pragma unroll
-        for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
-    }
-    wave_fence();
-    const C *tp = taps + a.unit_tap0[u];
-    const int grp = lane / kG, gl = lane % kG;
-    int4 nxt = a.runrec[r_beg + grp < r_end ? r_beg + grp : r_beg];
-    for (int rb = r_beg; rb < r_end; rb += kPer) {
-        const int r = rb + grp;
-        const bool valid = r < r_end;
-        const int4 rec = nxt;
-        if (rb + kPer < r_end) nxt = a.runrec[rb + kPer + grp < r_end ? rb + kPer + grp : rb + kPer];
-        const int nc = (rec.y >> 16) & 255, nrows = (rec.y >> 24) & 255, cell0 = rec.y & 0xFFFF;
-        const int ntap = valid ? nrows * nc : 0;
-        const float inv_nc = recip_nc(nc);
-        const C *rp = tp + rec.x;
-        R ar = 0, ai = 0;
-        for (int k0 = 0; __any(k0 < ntap); k0 += kG * kU) {
-            C K[kU];
-            int li[kU];
-#pragma unroll
-            for (int sl = 0; sl < kU; ++sl) {
-                K[sl].x = 0;
-                K[sl].y = 0;
-                li[sl] = cell0;
-                const int k = k0 + kG * sl + gl;
-                const bool ok = k < ntap;
-                if (__any(ok)) {
-                    const int kk = ok ? k : 0;
-                    const int row = sub_row(kk, inv_nc);
-                    li[sl] = sub_cell(cell0, kk, row, nc);
-                    if (ok) K[sl] = load_tap(rp + k);
-                }
-            }
-#pragma unroll
-            for (int sl = 0; sl < kU; ++sl) {
-                const C z = sb[li[sl]];
-                ar += K[sl].x * z.x - K[sl].y * z.y;
-                ai += K[sl].x * z.y + K[sl].y * z.x;
-            }
-        }
-#pragma unroll
-        for (int o = kG / 2; o > 0; o >>= 1) {
-            ar += __shfl_xor(ar, o, 64);
-            ai += __shfl_xor(ai, o, 64);
-        }
-        if (gl == 0 && valid) {
-            C o;
-            o.x = ar;
-            o.y = ai;
-            dpart[rec.w] = o;
-        }
-    }
+// yr[L] = yw of the visibility of run L (layout order), for k_grid_class.
+template <bool kFP64>
+__global__ void k_prep_runs(const typename Types<kFP64>::C *__restrict__ yw, const int4 *__restrict__ runrec,
+                            int64_t R, typename Types<kFP64>::C *yr) {
+    const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L < R) yr[L] = yw[runrec[L].z];
 }
 
 // y[perm[p]] = W_p (conj) sum of visibility p's run partials, in generation
 // order (its entries in turn, each entry's bands in turn): deterministic.
+// With lay, the partial of generation-order run g sits at dpart[lay[g]].
 template <bool kFP64>
 __global__ void k_degrid_reduce_runs(const typename Types<kFP64>::C *__restrict__ dpart,
                                      const int64_t *__restrict__ ent_off, const int32_t *__restrict__ run_first,
-                                     typename Types<kFP64>::C *vis, ApplyArgs a, int add_i) {
+                                     const int32_t *__restrict__ lay, typename Types<kFP64>::C *vis, ApplyArgs a,
+                                     int add_i) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1070,7 +999,7 @@ __global__ void k_degrid_reduce_runs(const typename Types<kFP64>::C *__restrict_
     R ar = 0, ai = 0;
     const int g1 = run_first[ent_off[p + 1]];
     for (int g = run_first[ent_off[p]]; g < g1; ++g) {
-        const C v = dpart[g];
+        const C v = dpart[lay ? lay[g] : g];
         ar += v.x;
         ai += v.y;
     }
@@ -1183,6 +1112,318 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_runs(const typename Typ
                 }
             }
         });
+    }
+    const uint32_t key = a.item_key[item];
+    C *dst;
+    int64_t ld;
+    if (sole) {
+        dst = tile_origin(grids, key, a.tile_bits, a.G);
+        ld = a.G;
+    } else {
+        dst = (C *)a.partial + (int64_t)a.item_slot[item] * kTile * kTile;
+        ld = kTile;
+    }
+    dst += (int64_t)band * kBR * ld;
+    wave_fence();
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) dst[(int64_t)r * ld + lane] = sb[r * kTile + lane];
+}
+
+// ---- exact kernels on run classes (contiguous-runs layout) ---------------
+// Neighbouring runs of one shape (same width, rows and first cell: the same
+// band cells) form a class; visibilities are dense in uv, so a class holds
+// tens of runs.  A wavefront serves a unit class by class with one lane per
+// tap of the shape: grid accumulates conj(K) y of the class's runs in
+// registers and updates the band once per class (no atomics, no conflicts);
+// degrid multiplies each run's taps by the band values it holds in registers
+// and sums them across the lanes.  Shapes of at most 64 taps use slices of W
+// lanes (W the next power of two), 64 / W runs at a time; longer shapes use
+// all 64 lanes per chunk of 64 taps.
+// runs per slice (short shapes) and runs (long shapes) whose loads are issued together
+constexpr int kDegridUnroll = 4, kDegridLongUnroll = 8;
+constexpr int kGridUnroll = 4, kGridLongUnroll = 8;
+
+// Sum over aligned blocks of W lanes with DPP moves; the block's sum ends in
+// its last lane.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add_src(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xF, false));
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_add_src(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, kRowMask, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, kRowMask, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int W, typename R>
+__device__ __forceinline__ R block_sum_last(R v) {
+    if constexpr (W >= 2) v += dpp_add_src<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    if constexpr (W >= 4) v += dpp_add_src<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    if constexpr (W >= 8) v += dpp_add_src<0x141, 0xF>(v);  // row_half_mirror
+    if constexpr (W >= 16) v += dpp_add_src<0x140, 0xF>(v); // row_mirror
+    if constexpr (W >= 32) v += dpp_add_src<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
+    if constexpr (W >= 64) v += dpp_add_src<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+__device__ __forceinline__ int pow2_at_least(int x) {
+    int w = 1;
+    while (w < x) w <<= 1;
+    return w;
+}
+
+// Degrid of one class with slices of W lanes (shape of L <= W taps).
+// Run partials go to dpart in layout order (dpart[run0 + i]).
+template <bool kFP64, int W>
+__device__ __forceinline__ void degrid_class_small(const typename Types<kFP64>::C *__restrict__ tp,
+                                                   typename Types<kFP64>::C z, int L, int m,
+                                                   typename Types<kFP64>::C *dpart, int lane) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    constexpr int P = 64 / W;
+    const int sl = lane / W, kk = lane % W;
+    const bool act = kk < L;
+    for (int i0 = 0; i0 < m; i0 += P * kDegridUnroll) {
+        C K[kDegridUnroll];
+#pragma unroll
+        for (int j = 0; j < kDegridUnroll; ++j) {
+            const int i = i0 + j * P + sl;
+            K[j].x = 0;
+            K[j].y = 0;
+            if (act && i < m) K[j] = load_tap(tp + (uint32_t)(i * L + kk));
+        }
+#pragma unroll
+        for (int j = 0; j < kDegridUnroll; ++j) {
+            R pr = K[j].x * z.x - K[j].y * z.y;
+            R pi = K[j].x * z.y + K[j].y * z.x;
+            pr = block_sum_last<W>(pr);
+            pi = block_sum_last<W>(pi);
+            const int i = i0 + j * P + sl;
+            if (kk == W - 1 && i < m) {
+                C o;
+                o.x = pr;
+                o.y = pi;
+                dpart[i] = o;
+            }
+        }
+    }
+}
+
+template <bool kFP64, int kBR>
+__global__ __launch_bounds__(64 * kRunWaves) void k_degrid_class(const typename Types<kFP64>::C *__restrict__ taps,
+                                                                 const typename Types<kFP64>::C *__restrict__ grids,
+                                                                 typename Types<kFP64>::C *dpart, RunArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    __shared__ C s_band[kRunWaves][kBR * kTile];
+    const int wid = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
+    if (u >= a.n_units) return;  // uniform over the wavefront
+    const int c_beg = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
+    if (c_beg >= c_end) return;
+    constexpr int kNB = kTile / kBR;
+    const int item = (int)(u / kNB), band = (int)(u % kNB);
+    C *sb = s_band[wid];
+    {
+        const C *src = tile_origin(grids, a.item_key[item], a.tile_bits, a.G) + (int64_t)band * kBR * a.G;
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
+    }
+    wave_fence();
+    const C *tu = taps + a.unit_tap0[u];
+    for (int c = c_beg; c < c_end; ++c) {
+        const int4 cr = a.clsrec[c];
+        const int nc = (cr.w >> 16) & 255, nrows = (cr.w >> 24) & 255, cell0 = cr.w & 0xFFFF;
+        const int L = nc * nrows, run0 = cr.y, m = cr.z;
+        const C *tp = tu + cr.x;
+        if (L <= 64) {
+            const int W = pow2_at_least(L);
+            const int kk = lane % W;
+            C z;
+            z.x = 0;
+            z.y = 0;
+            if (kk < L) z = sb[cell0 + (kk / nc) * kTile + kk % nc];
+            C *dp = dpart + run0;
+            switch (W) {
+            case 1: degrid_class_small<kFP64, 1>(tp, z, L, m, dp, lane); break;
+            case 2: degrid_class_small<kFP64, 2>(tp, z, L, m, dp, lane); break;
+            case 4: degrid_class_small<kFP64, 4>(tp, z, L, m, dp, lane); break;
+            case 8: degrid_class_small<kFP64, 8>(tp, z, L, m, dp, lane); break;
+            case 16: degrid_class_small<kFP64, 16>(tp, z, L, m, dp, lane); break;
+            case 32: degrid_class_small<kFP64, 32>(tp, z, L, m, dp, lane); break;
+            default: degrid_class_small<kFP64, 64>(tp, z, L, m, dp, lane); break;
+            }
+        } else {
+            // long shapes: kDegridLongUnroll runs at a time, 64 taps per step, band values from LDS
+            for (int i0 = 0; i0 < m; i0 += kDegridLongUnroll) {
+                R pr[kDegridLongUnroll], pi[kDegridLongUnroll];
+#pragma unroll
+                for (int j = 0; j < kDegridLongUnroll; ++j) pr[j] = pi[j] = 0;
+                for (int k0 = 0; k0 < L; k0 += 64) {
+                    const int k = k0 + lane;
+                    C K[kDegridLongUnroll];
+#pragma unroll
+                    for (int j = 0; j < kDegridLongUnroll; ++j) {
+                        K[j].x = 0;
+                        K[j].y = 0;
+                        if (k < L && i0 + j < m) K[j] = load_tap(tp + (uint32_t)((i0 + j) * L + k));
+                    }
+                    C z;
+                    z.x = 0;
+                    z.y = 0;
+                    if (k < L) z = sb[cell0 + (k / nc) * kTile + k % nc];
+#pragma unroll
+                    for (int j = 0; j < kDegridLongUnroll; ++j) {
+                        pr[j] += K[j].x * z.x - K[j].y * z.y;
+                        pi[j] += K[j].x * z.y + K[j].y * z.x;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kDegridLongUnroll; ++j) {
+                    const R sr = block_sum_last<64>(pr[j]);
+                    const R si = block_sum_last<64>(pi[j]);
+                    if (lane == 63 && i0 + j < m) {
+                        C o;
+                        o.x = sr;
+                        o.y = si;
+                        dpart[run0 + i0 + j] = o;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Grid of one class with slices of W lanes: returns the lane's sum over the
+// class's runs of conj(K) y for its tap (slices combined).
+// yr: the class's runs' weighted visibilities, in layout order.
+template <bool kFP64, int W>
+__device__ __forceinline__ typename Types<kFP64>::C grid_class_small(const typename Types<kFP64>::C *__restrict__ tp,
+                                                                     const typename Types<kFP64>::C *__restrict__ yr,
+                                                                     int L, int m, int lane) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    constexpr int P = 64 / W;
+    const int sl = lane / W, kk = lane % W;
+    const bool act = kk < L;
+    R ar = 0, ai = 0;
+    for (int i0 = 0; i0 < m; i0 += P * kGridUnroll) {
+        C K[kGridUnroll], y[kGridUnroll];
+#pragma unroll
+        for (int j = 0; j < kGridUnroll; ++j) {
+            const int i = i0 + j * P + sl;
+            K[j].x = K[j].y = y[j].x = y[j].y = 0;
+            if (i < m) y[j] = yr[i];
+            if (act && i < m) K[j] = load_tap(tp + (uint32_t)(i * L + kk));
+        }
+#pragma unroll
+        for (int j = 0; j < kGridUnroll; ++j) {
+            ar += K[j].x * y[j].x + K[j].y * y[j].y;  // conj(K) y
+            ai += K[j].x * y[j].y - K[j].y * y[j].x;
+        }
+    }
+#pragma unroll
+    for (int o = W; o < 64; o <<= 1) {  // slices hold other runs of the same taps
+        ar += __shfl_xor(ar, o, 64);
+        ai += __shfl_xor(ai, o, 64);
+    }
+    C out;
+    out.x = ar;
+    out.y = ai;
+    return out;
+}
+
+// Grid on run classes: the band accumulates in LDS, class by class (a unit's
+// classes are sorted by length, longest first).
+template <bool kFP64, int kBR>
+__global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Types<kFP64>::C *__restrict__ taps,
+                                                               const typename Types<kFP64>::C *__restrict__ yr,
+                                                               typename Types<kFP64>::C *grids, RunArgs a) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    __shared__ C s_band[kRunWaves][kBR * kTile];
+    const int wid = wave_index();
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
+    if (u >= a.n_units) return;  // uniform over the wavefront
+    const int c_beg = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
+    constexpr int kNB = kTile / kBR;
+    const int item = (int)(u / kNB), band = (int)(u % kNB);
+    const bool sole = a.item_sole[item] != 0;
+    if (sole && c_beg >= c_end) return;  // nothing to add to a band the zero pass cleared
+    C *sb = s_band[wid];
+    C zero;
+    zero.x = 0;
+    zero.y = 0;
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = zero;
+    wave_fence();
+    const C *tu = taps + a.unit_tap0[u];
+    for (int c = c_beg; c < c_end; ++c) {
+        const int4 cr = a.clsrec[c];
+        const int nc = (cr.w >> 16) & 255, nrows = (cr.w >> 24) & 255, cell0 = cr.w & 0xFFFF;
+        const int L = nc * nrows, run0 = cr.y, m = cr.z;
+        const C *tp = tu + cr.x;
+        if (L <= 64) {
+            const int W = pow2_at_least(L);
+            C acc;
+            const C *yc = yr + run0;
+            switch (W) {
+            case 1: acc = grid_class_small<kFP64, 1>(tp, yc, L, m, lane); break;
+            case 2: acc = grid_class_small<kFP64, 2>(tp, yc, L, m, lane); break;
+            case 4: acc = grid_class_small<kFP64, 4>(tp, yc, L, m, lane); break;
+            case 8: acc = grid_class_small<kFP64, 8>(tp, yc, L, m, lane); break;
+            case 16: acc = grid_class_small<kFP64, 16>(tp, yc, L, m, lane); break;
+            case 32: acc = grid_class_small<kFP64, 32>(tp, yc, L, m, lane); break;
+            default: acc = grid_class_small<kFP64, 64>(tp, yc, L, m, lane); break;
+            }
+            if (lane < L) {  // slice 0 holds the combined sums; the class's cells are distinct
+                const int cell = cell0 + (lane / nc) * kTile + lane % nc;
+                C v = sb[cell];
+                v.x += acc.x;
+                v.y += acc.y;
+                sb[cell] = v;
+            }
+        } else {
+            // long shapes (> 64 taps): the class's taps in order, 64 consecutive taps per
+            // step, so the 64 lanes of a step hold distinct taps of at most two runs, on
+            // distinct cells: a plain read-modify-write per step
+            const float inv_nc = recip_nc(nc);
+            const int total = m * L;
+            int i = 0, k = lane;  // run and tap of the lane's current tap (L > 64: lane < L)
+            for (int t0 = 0; t0 < total; t0 += 64 * kGridLongUnroll) {
+                C K[kGridLongUnroll], y[kGridLongUnroll];
+                int cell[kGridLongUnroll];
+#pragma unroll
+                for (int j = 0; j < kGridLongUnroll; ++j) {
+                    const bool on = t0 + 64 * j + lane < total;
+                    K[j].x = K[j].y = y[j].x = y[j].y = 0;
+                    cell[j] = 0;
+                    if (on) {
+                        K[j] = load_tap(tp + t0 + 64 * j + lane);
+                        y[j] = yr[run0 + i];
+                        const int row = sub_row(k, inv_nc);
+                        cell[j] = sub_cell(cell0, k, row, nc);
+                    }
+                    k += 64;
+                    if (k >= L) {  // one wrap at most: L > 64
+                        k -= L;
+                        ++i;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kGridLongUnroll; ++j) {
+                    if (t0 + 64 * j + lane < total) {
+                        C v = sb[cell[j]];
+                        v.x += K[j].x * y[j].x + K[j].y * y[j].y;  // conj(K) y
+                        v.y += K[j].x * y[j].y - K[j].y * y[j].x;
+                        sb[cell[j]] = v;
+                    }
+                }
+            }
+        }
     }
     const uint32_t key = a.item_key[item];
     C *dst;
@@ -1460,9 +1701,18 @@ hipError_t fft_exec(wsp_ctx *c, bool forward, hipStream_t s) {
     return hipSuccess;
 }
 
+// Grid kernel choice for the contiguous-runs layout: when most taps are in
+// shapes longer than 64 taps (large supports), k_grid_runs streams each band's
+// taps in 64-tap steps with fewer registers and outruns the class kernel
+// (measured on 1024^2 single-stack and 4096^2 16-stack MWA-like workloads);
+// otherwise k_grid_class accumulates each class in registers.
+static bool grid_on_runs(const Plan &pl) { return 2 * pl.long_taps > pl.total_taps; }
+
 RunArgs run_args(const wsp_ctx *c) {
     const Plan &pl = c->plan;
     RunArgs r{};
+    r.clsrec = pl.clsrec;
+    r.unit_cls0 = pl.unit_cls0;
     r.runrec = pl.runrec;
     r.unit_run0 = pl.unit_run0;
     r.unit_tap0 = pl.unit_tap0;
@@ -1542,24 +1792,20 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     if (!g.planes) {
         const RunArgs ra = run_args(c);
         if (ra.n_units > 0) {
-            // group width from the mean run length
-            const int64_t mean_run = pl.n_runs > 0 ? pl.total_taps / pl.n_runs : 1;
             const dim3 gd(blocks(ra.n_units, kRunWaves)), bd(64 * kRunWaves);
             if (pl.interleaved) {
                 if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_lanes<kFP64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
                 else hipLaunchKernelGGL((k_degrid_lanes<kFP64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
             } else if (pl.tile_band_rows == 16) {
-                if (mean_run < 48) hipLaunchKernelGGL((k_degrid_runs<kFP64, 8, 16>), gd, bd, 0, s, tp, gr, dp, ra);
-                else if (mean_run < 192) hipLaunchKernelGGL((k_degrid_runs<kFP64, 16, 16>), gd, bd, 0, s, tp, gr, dp, ra);
-                else hipLaunchKernelGGL((k_degrid_runs<kFP64, 64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
+                hipLaunchKernelGGL((k_degrid_class<kFP64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
             } else {
-                if (mean_run < 48) hipLaunchKernelGGL((k_degrid_runs<kFP64, 8, 8>), gd, bd, 0, s, tp, gr, dp, ra);
-                else if (mean_run < 192) hipLaunchKernelGGL((k_degrid_runs<kFP64, 16, 8>), gd, bd, 0, s, tp, gr, dp, ra);
-                else hipLaunchKernelGGL((k_degrid_runs<kFP64, 64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
+                hipLaunchKernelGGL((k_degrid_class<kFP64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
             }
         }
+        // class kernels write run partials in layout order
+        const int32_t *lay = pl.interleaved ? nullptr : pl.run_lay;
         hipLaunchKernelGGL(k_degrid_reduce_runs<kFP64>, dim3(blocks(a.m, 256)), dim3(256), 0, s, (const C *)dp,
-                           pl.ent_off, pl.run_first, (C *)vis, a, add_i);
+                           pl.ent_off, pl.run_first, lay, (C *)vis, a, add_i);
         stage_end(c, kStDegrid, ev, s);
         return hipGetLastError();
     }
@@ -1608,10 +1854,16 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
         if (ra.n_units > 0 && pl.interleaved) {
             if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_lanes<kFP64, 16>), gd, bd, 0, s, tp, yw, gr, ra);
             else hipLaunchKernelGGL((k_grid_lanes<kFP64, 8>), gd, bd, 0, s, tp, yw, gr, ra);
-        } else if (ra.n_units > 0 && pl.tile_band_rows == 16) {
-            hipLaunchKernelGGL((k_grid_runs<kFP64, 16>), gd, bd, 0, s, tp, yw, gr, ra);
+        } else if (ra.n_units > 0 && grid_on_runs(pl)) {
+            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_runs<kFP64, 16>), gd, bd, 0, s, tp, yw, gr, ra);
+            else hipLaunchKernelGGL((k_grid_runs<kFP64, 8>), gd, bd, 0, s, tp, yw, gr, ra);
         } else if (ra.n_units > 0) {
-            hipLaunchKernelGGL((k_grid_runs<kFP64, 8>), gd, bd, 0, s, tp, yw, gr, ra);
+            // each run's weighted visibility in layout order (the partials' space is free here)
+            C *yr = (C *)c->scratch_dpart;
+            hipLaunchKernelGGL(k_prep_runs<kFP64>, dim3(blocks(pl.n_runs, 256)), dim3(256), 0, s, yw, pl.runrec,
+                               pl.n_runs, yr);
+            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_class<kFP64, 16>), gd, bd, 0, s, tp, yr, gr, ra);
+            else hipLaunchKernelGGL((k_grid_class<kFP64, 8>), gd, bd, 0, s, tp, yr, gr, ra);
         }
     } else if constexpr (!kFP64) {  // w-plane kernels (FP32 path only)
         if (pl.n_items > 0) {

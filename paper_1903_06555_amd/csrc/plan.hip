@@ -423,8 +423,11 @@ __global__ void k_item_marks(const int32_t *__restrict__ item_start, int n_items
     if (i >= 1 && i < n_items) marks[item_start[i]] = 1;
 }
 
-// Runs in generation order: sort key (item, band, longest first), tap count
-// and entry.  Equal keys keep generation order (the radix sort is stable).
+// Runs in generation order: sort key (item, band, longest first, then the
+// run's shape: width and first cell), tap count and entry.  Runs of one
+// shape (same width, rows and first cell, so the same cells) become
+// neighbours, a "class".  Equal keys keep generation order (the radix sort
+// is stable).
 __global__ void k_run_keys(const int4 *__restrict__ ent, const int32_t *__restrict__ run_first,
                            const int32_t *__restrict__ pos_of, const int32_t *__restrict__ item_of_pos,
                            int64_t E, int br, uint64_t *key, int32_t *gidx, int32_t *rlen, int32_t *rent) {
@@ -442,7 +445,9 @@ __global__ void k_run_keys(const int4 *__restrict__ ent, const int32_t *__restri
         const int lo = ly0 > b * br ? ly0 : b * br;
         const int hi = (ly0 + nr < (b + 1) * br) ? ly0 + nr : (b + 1) * br;
         const int len = (hi - lo) * nc;  // <= 16 * 64
-        key[g] = (it << 15) | ((uint64_t)b << 11) | (uint64_t)(2047 - len);
+        const int cell0 = (lo - b * br) * kTile + ((z >> 16) & 255);
+        key[g] = (it << 32) | ((uint64_t)b << 28) | ((uint64_t)(2047 - len) << 17) | ((uint64_t)nc << 10) |
+                 (uint64_t)cell0;
         gidx[g] = g;
         rlen[g] = len;
         rent[g] = (int32_t)e;
@@ -450,7 +455,7 @@ __global__ void k_run_keys(const int4 *__restrict__ ent, const int32_t *__restri
 }
 
 __device__ __forceinline__ int64_t run_unit(uint64_t key, int bands) {
-    return (int64_t)(key >> 15) * bands + (int64_t)((key >> 11) & 15);
+    return (int64_t)(key >> 32) * bands + (int64_t)((key >> 28) & 15);
 }
 
 __global__ void k_run_lengths(const int32_t *__restrict__ lay2gen, const int32_t *__restrict__ rlen,
@@ -464,6 +469,12 @@ __global__ void k_run_taps(const int32_t *__restrict__ lay2gen, const int64_t *_
                            int64_t R, int64_t *run_tap) {
     int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (L < R) run_tap[lay2gen[L]] = start_lay[L];
+}
+
+// Layout position of each generation-order run.
+__global__ void k_run_slots(const int32_t *__restrict__ lay2gen, int64_t R, int32_t *run_lay) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L < R) run_lay[lay2gen[L]] = (int32_t)L;
 }
 
 // First run of each unit (units without runs take the next unit's first run).
@@ -486,7 +497,7 @@ __global__ void k_unit_taps(const int32_t *__restrict__ unit_run0, const int64_t
 
 // Record of the run in layout position L, stored at slot[L] (or L).
 __device__ __forceinline__ int4 run_record(uint64_t key, const int4 &en, int br, int rel, int gen) {
-    const int b = (int)((key >> 11) & 15);
+    const int b = (int)((key >> 28) & 15);
     const int z = en.z;
     const int nc = z & 255, nr = (z >> 8) & 255, lx0 = (z >> 16) & 255, ly0 = (z >> 24) & 255;
     const int lo = ly0 > b * br ? ly0 : b * br;
@@ -504,6 +515,47 @@ __global__ void k_run_records(const uint64_t *__restrict__ keys, const int32_t *
     const uint64_t key = keys[L];
     const int g = lay2gen[L];
     runrec[L] = run_record(key, ent[rent[g]], br, (int)(start_lay[L] - unit_tap0[run_unit(key, kTile / br)]), g);
+}
+
+// ---- run classes (contiguous-runs layout): neighbouring runs of one shape
+__global__ void k_class_heads(const uint64_t *__restrict__ keys, int64_t R, int32_t *head) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L < R) head[L] = (L == 0 || keys[L] != keys[L - 1]) ? 1 : 0;
+}
+
+// Class of each head run (inclusive scan of the heads, minus one): its first
+// run and that run's key.
+__global__ void k_class_first(const int32_t *__restrict__ head, const int32_t *__restrict__ cls_incl,
+                              const uint64_t *__restrict__ keys, int64_t R, int32_t *cls_run0, uint64_t *cls_key) {
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= R || !head[L]) return;
+    const int c = cls_incl[L] - 1;
+    cls_run0[c] = (int32_t)L;
+    cls_key[c] = keys[L];
+}
+
+// clsrec[c] = {first tap relative to the unit, first run, runs, cell0 | nc << 16 | nrows << 24}.
+__global__ void k_class_records(const int32_t *__restrict__ cls_run0, const uint64_t *__restrict__ cls_key,
+                                const int4 *__restrict__ runrec, int64_t n_cls, int64_t R, int4 *clsrec) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cls) return;
+    const int r0 = cls_run0[c];
+    const int r1 = c + 1 < n_cls ? cls_run0[c + 1] : (int)R;
+    const int4 rr = runrec[r0];
+    clsrec[c] = make_int4(rr.x, r0, r1 - r0, rr.y);
+}
+
+// Taps in classes whose shape has more than 64 taps.
+__global__ void k_long_taps(const int4 *__restrict__ clsrec, int64_t n_cls, unsigned long long *out) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (c < n_cls) {
+        const int4 cr = clsrec[c];
+        const int L = ((cr.w >> 16) & 255) * ((cr.w >> 24) & 255);
+        if (L > 64) v = (unsigned long long)L * (unsigned long long)cr.z;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
 }
 
 // ---- interleaved variant: units padded to whole groups of 64 runs
@@ -723,10 +775,13 @@ void free_sorted_plan(Plan &pl) {
     pl.ptw = nullptr;
     pl.n_pairs = 0;
     pl.table_len = 0;
-    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec, pl.unit_run0, pl.unit_tap0,
-                     pl.run_lay,   pl.len16,   pl.suf,    pl.grp_tap};
+    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec,  pl.unit_run0, pl.unit_tap0,
+                     pl.run_lay,   pl.len16,   pl.suf,     pl.grp_tap,   pl.clsrec, pl.unit_cls0};
     for (void *q : rptrs) dfree(q);
-    pl.run_first = pl.unit_run0 = pl.run_lay = nullptr;
+    pl.run_first = pl.unit_run0 = pl.run_lay = pl.unit_cls0 = nullptr;
+    pl.clsrec = nullptr;
+    pl.n_classes = 0;
+    pl.long_taps = 0;
     pl.run_tap = pl.unit_tap0 = pl.grp_tap = nullptr;
     pl.runrec = nullptr;
     pl.len16 = nullptr;
@@ -1222,16 +1277,16 @@ static hipError_t make_runs(Plan &pl, hipStream_t s) {
     WSP_RSTEP(hipGetLastError());
     int item_bits = 1;
     while (((int64_t)1 << item_bits) < (int64_t)pl.n_items) ++item_bits;
-    if (15 + item_bits > 64) {
+    if (32 + item_bits > 64) {
         cleanup();
         return hipErrorInvalidValue;
     }
     need = 0;
     WSP_RSTEP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key, key_sorted, gidx, lay2gen, (int)R, 0,
-                                                 15 + item_bits, s));
+                                                 32 + item_bits, s));
     WSP_RSTEP(scratch(need));
     WSP_RSTEP(hipcub::DeviceRadixSort::SortPairs(tmp, need, key, key_sorted, gidx, lay2gen, (int)R, 0,
-                                                 15 + item_bits, s));
+                                                 32 + item_bits, s));
     // units (runs in unpadded layout order)
     WSP_RSTEP(dalloc(&pl.unit_run0, U + 1));
     WSP_RSTEP(dalloc(&pl.unit_tap0, U + 1));
@@ -1259,12 +1314,57 @@ static hipError_t make_runs(Plan &pl, hipStream_t s) {
     WSP_RSTEP(scratch(need));
     WSP_RSTEP(hipcub::DeviceScan::ExclusiveSum(tmp, need, len_lay, start_lay, (int)(R + 1), s));
     hipLaunchKernelGGL(k_run_taps, dim3(grid1d(R, 256)), dim3(256), 0, s, lay2gen, start_lay, R, pl.run_tap);
+    WSP_RSTEP(dalloc(&pl.run_lay, R));
+    hipLaunchKernelGGL(k_run_slots, dim3(grid1d(R, 256)), dim3(256), 0, s, lay2gen, R, pl.run_lay);
     hipLaunchKernelGGL(k_unit_taps, dim3(grid1d(U + 1, 256)), dim3(256), 0, s, pl.unit_run0, start_lay, U,
                        pl.unit_tap0);
     WSP_RSTEP(dalloc(&pl.runrec, R));
     hipLaunchKernelGGL(k_run_records, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, lay2gen, start_lay,
                        pl.unit_tap0, rent, pl.ent, R, br, pl.runrec);
     WSP_RSTEP(hipGetLastError());
+    // classes: maximal sequences of runs of one shape within a unit (the key
+    // holds the unit and the shape)
+    {
+        int32_t *head = gidx, *incl = rlen;  // both free now
+        uint64_t *cls_key = key;
+        WSP_RSTEP(dalloc(&pad_cnt, R + 1));   // first run of each class
+        int32_t *cls_run0 = pad_cnt;
+        if (R > 0) {
+            hipLaunchKernelGGL(k_class_heads, dim3(grid1d(R, 256)), dim3(256), 0, s, key_sorted, R, head);
+            need = 0;
+            WSP_RSTEP(hipcub::DeviceScan::InclusiveSum(nullptr, need, head, incl, (int)R, s));
+            WSP_RSTEP(scratch(need));
+            WSP_RSTEP(hipcub::DeviceScan::InclusiveSum(tmp, need, head, incl, (int)R, s));
+            int32_t nc32 = 0;
+            WSP_RSTEP(hipMemcpyAsync(&nc32, incl + R - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            WSP_RSTEP(hipStreamSynchronize(s));
+            pl.n_classes = nc32;
+            hipLaunchKernelGGL(k_class_first, dim3(grid1d(R, 256)), dim3(256), 0, s, head, incl, key_sorted, R,
+                               cls_run0, cls_key);
+        } else {
+            pl.n_classes = 0;
+        }
+        WSP_RSTEP(dalloc(&pl.clsrec, pl.n_classes));
+        WSP_RSTEP(dalloc(&pl.unit_cls0, U + 1));
+        if (pl.n_classes > 0) {
+            hipLaunchKernelGGL(k_class_records, dim3(grid1d(pl.n_classes, 256)), dim3(256), 0, s, cls_run0,
+                               cls_key, pl.runrec, pl.n_classes, R, pl.clsrec);
+            hipLaunchKernelGGL(k_unit_heads, dim3(grid1d(pl.n_classes, 256)), dim3(256), 0, s, cls_key,
+                               pl.n_classes, U, pl.tile_bands, pl.unit_cls0);
+            WSP_RSTEP(dalloc(&steps, 1));
+            unsigned long long *d_long = steps;
+            WSP_RSTEP(hipMemsetAsync(d_long, 0, sizeof(unsigned long long), s));
+            hipLaunchKernelGGL(k_long_taps, dim3(grid1d(pl.n_classes, 256)), dim3(256), 0, s, pl.clsrec,
+                               pl.n_classes, d_long);
+            unsigned long long h_long = 0;
+            WSP_RSTEP(hipMemcpyAsync(&h_long, d_long, sizeof(h_long), hipMemcpyDeviceToHost, s));
+            WSP_RSTEP(hipStreamSynchronize(s));
+            pl.long_taps = (int64_t)h_long;
+        } else {
+            WSP_RSTEP(hipMemsetAsync(pl.unit_cls0, 0, sizeof(int32_t) * (size_t)(U + 1), s));
+        }
+        WSP_RSTEP(hipGetLastError());
+    }
     int64_t total = 0;
     WSP_RSTEP(hipMemcpyAsync(&total, start_lay + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     WSP_RSTEP(hipStreamSynchronize(s));  // before the temporaries are released

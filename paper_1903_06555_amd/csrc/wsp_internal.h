@@ -210,6 +210,14 @@ struct Plan {
                                   // group, interleaved) relative to its unit, cell0 | nc << 16 |
                                   // nrows << 24, visibility, generation index (-1: padding)}
                                   // (cell0: band-relative tile cell of the run's first tap)
+    // Contiguous-runs layout: within a unit, runs of one shape (width, rows,
+    // first cell) are neighbours (a class); their taps are consecutive blocks
+    // of equal length.
+    int64_t n_classes = 0;
+    int64_t long_taps = 0;        // taps in classes of more than 64 taps per run
+    int4 *clsrec = nullptr;       // [n_classes] {first tap relative to its unit, first run (layout),
+                                  // runs, cell0 | nc << 16 | nrows << 24}
+    int32_t *unit_cls0 = nullptr; // [n_items * bands + 1] first class of each unit
     int32_t *unit_run0 = nullptr; // [n_items * bands + 1] first run (layout order) of each unit
     int64_t *unit_tap0 = nullptr; // [n_items * bands + 1] first tap of each unit
 };

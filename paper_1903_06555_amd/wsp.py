@@ -108,6 +108,8 @@ class wsp_plan_info(ctypes.Structure):
         ("band_rows", ctypes.c_int32),
         ("tap_layout", ctypes.c_int32),
         ("group_steps", ctypes.c_int64),
+        ("classes", ctypes.c_int64),
+        ("long_taps", ctypes.c_int64),
     ]
 
 
