@@ -57,6 +57,8 @@ def parse():
                     help="exact per-visibility taps, or taps interpolated from 1-D w-planes")
     ap.add_argument("--band-rows", type=int, default=0, choices=[0, 8, 16],
                     help="exact mode: tile rows per band of the tap layout (0: the library's choice)")
+    ap.add_argument("--item-taps", type=int, default=0,
+                    help="exact mode: taps per tile work item (0: the library's default, 2^19)")
     ap.add_argument("--tap-layout", default="auto", choices=["auto", "runs", "interleaved"],
                     help="exact mode: tap layout (auto: interleaved when runs are short)")
     ap.add_argument("--mode", default="operator", choices=["operator", "copy", "serving", "build"],
@@ -459,7 +461,7 @@ def build_rate(args):
 
 
 def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_override=None,
-                 want_y: bool = False, band_rows: int = 0, tap_layout: str = "auto"):
+                 want_y: bool = False, band_rows: int = 0, tap_layout: str = "auto", item_taps: int = 0):
     """Plan, build and time `steps` operator steps of one workload; returns a dict."""
     import torch
 
@@ -477,7 +479,7 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
     planes = kernels == "planes"
     params = wsp.make_params(wl.n, math.radians(wl.fov_deg), n_stacks=wl.n_stacks, fold=wl.fold,
                              precision=precision, kernels=kernels, band_rows=band_rows,
-                             tap_layout=tap_layout)
+                             tap_layout=tap_layout, item_taps=item_taps)
     t0 = time.perf_counter()
     op = wsp.Operator(params, uvw, build=False)
     torch.cuda.synchronize()
@@ -598,7 +600,7 @@ def main():
     wl = syn.WORKLOADS[args.workload]
     precision = args.precision or wl.precision
     head = run_operator(wl, precision, args.kernels, args.steps, args.warmup, args.m_vis, want_y=True,
-                        band_rows=args.band_rows, tap_layout=args.tap_layout)
+                        band_rows=args.band_rows, tap_layout=args.tap_layout, item_taps=args.item_taps)
     uvw = head.pop("_uvw")
     planes = args.kernels == "planes"
     result = {

@@ -1210,30 +1210,31 @@ __device__ __forceinline__ void degrid_class_small(const typename Types<kFP64>::
     }
 }
 
+// A block serves one band: its kRunWaves wavefronts stage the band together
+// and then take every kRunWaves-th class each (classes are independent in
+// degrid), so that a large band is not left to one wavefront at the end of
+// the launch (a wavefront streams at a small fraction of the chip's rate).
 template <bool kFP64, int kBR>
 __global__ __launch_bounds__(64 * kRunWaves) void k_degrid_class(const typename Types<kFP64>::C *__restrict__ taps,
                                                                  const typename Types<kFP64>::C *__restrict__ grids,
                                                                  typename Types<kFP64>::C *dpart, RunArgs a) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    __shared__ C s_band[kRunWaves][kBR * kTile];
+    __shared__ C sb[kBR * kTile];
     const int wid = wave_index();
     const int lane = threadIdx.x & 63;
-    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
-    if (u >= a.n_units) return;  // uniform over the wavefront
-    const int c_beg = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
-    if (c_beg >= c_end) return;
+    const int64_t u = blockIdx.x;
+    const int c_first = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
+    if (c_first >= c_end) return;  // uniform over the block
     constexpr int kNB = kTile / kBR;
     const int item = (int)(u / kNB), band = (int)(u % kNB);
-    C *sb = s_band[wid];
     {
         const C *src = tile_origin(grids, a.item_key[item], a.tile_bits, a.G) + (int64_t)band * kBR * a.G;
-#pragma unroll
-        for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
+        for (int r = wid; r < kBR; r += kRunWaves) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
     }
-    wave_fence();
+    __syncthreads();
     const C *tu = taps + a.unit_tap0[u];
-    for (int c = c_beg; c < c_end; ++c) {
+    for (int c = c_first + wid; c < c_end; c += kRunWaves) {
         const int4 cr = a.clsrec[c];
         const int nc = (cr.w >> 16) & 255, nrows = (cr.w >> 24) & 255, cell0 = cr.w & 0xFFFF;
         const int L = nc * nrows, run0 = cr.y, m = cr.z;
@@ -1335,8 +1336,10 @@ __device__ __forceinline__ typename Types<kFP64>::C grid_class_small(const typen
     return out;
 }
 
-// Grid on run classes: the band accumulates in LDS, class by class (a unit's
-// classes are sorted by length, longest first).
+// Grid on run classes: a block serves one band; each of its wavefronts takes
+// every kRunWaves-th class and accumulates into its own copy of the band in
+// LDS (a class's cells are distinct; classes go in program order), then the
+// block sums the copies in wavefront order (deterministic) and stores the band.
 template <bool kFP64, int kBR>
 __global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Types<kFP64>::C *__restrict__ taps,
                                                                const typename Types<kFP64>::C *__restrict__ yr,
@@ -1346,13 +1349,12 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Ty
     __shared__ C s_band[kRunWaves][kBR * kTile];
     const int wid = wave_index();
     const int lane = threadIdx.x & 63;
-    const int64_t u = (int64_t)blockIdx.x * kRunWaves + wid;
-    if (u >= a.n_units) return;  // uniform over the wavefront
-    const int c_beg = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
+    const int64_t u = blockIdx.x;
+    const int c_first = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
     constexpr int kNB = kTile / kBR;
     const int item = (int)(u / kNB), band = (int)(u % kNB);
     const bool sole = a.item_sole[item] != 0;
-    if (sole && c_beg >= c_end) return;  // nothing to add to a band the zero pass cleared
+    if (sole && c_first >= c_end) return;  // uniform over the block: the zero pass cleared the band
     C *sb = s_band[wid];
     C zero;
     zero.x = 0;
@@ -1361,7 +1363,7 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Ty
     for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = zero;
     wave_fence();
     const C *tu = taps + a.unit_tap0[u];
-    for (int c = c_beg; c < c_end; ++c) {
+    for (int c = c_first + wid; c < c_end; c += kRunWaves) {
         const int4 cr = a.clsrec[c];
         const int nc = (cr.w >> 16) & 255, nrows = (cr.w >> 24) & 255, cell0 = cr.w & 0xFFFF;
         const int L = nc * nrows, run0 = cr.y, m = cr.z;
@@ -1436,9 +1438,17 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Ty
         ld = kTile;
     }
     dst += (int64_t)band * kBR * ld;
-    wave_fence();
+    __syncthreads();
+    for (int r = wid; r < kBR; r += kRunWaves) {
+        C v = s_band[0][r * kTile + lane];
 #pragma unroll
-    for (int r = 0; r < kBR; ++r) dst[(int64_t)r * ld + lane] = sb[r * kTile + lane];
+        for (int w = 1; w < kRunWaves; ++w) {
+            const C t = s_band[w][r * kTile + lane];
+            v.x += t.x;
+            v.y += t.y;
+        }
+        dst[(int64_t)r * ld + lane] = v;
+    }
 }
 
 // ---- exact kernels on the interleaved tap layout -------------------------
@@ -1796,10 +1806,10 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
             if (pl.interleaved) {
                 if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_lanes<kFP64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
                 else hipLaunchKernelGGL((k_degrid_lanes<kFP64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
-            } else if (pl.tile_band_rows == 16) {
-                hipLaunchKernelGGL((k_degrid_class<kFP64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
             } else {
-                hipLaunchKernelGGL((k_degrid_class<kFP64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
+                const dim3 gs((unsigned)ra.n_units);  // one block per band
+                if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_class<kFP64, 16>), gs, bd, 0, s, tp, gr, dp, ra);
+                else hipLaunchKernelGGL((k_degrid_class<kFP64, 8>), gs, bd, 0, s, tp, gr, dp, ra);
             }
         }
         // class kernels write run partials in layout order
@@ -1862,8 +1872,9 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
             C *yr = (C *)c->scratch_dpart;
             hipLaunchKernelGGL(k_prep_runs<kFP64>, dim3(blocks(pl.n_runs, 256)), dim3(256), 0, s, yw, pl.runrec,
                                pl.n_runs, yr);
-            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_class<kFP64, 16>), gd, bd, 0, s, tp, yr, gr, ra);
-            else hipLaunchKernelGGL((k_grid_class<kFP64, 8>), gd, bd, 0, s, tp, yr, gr, ra);
+            const dim3 gs((unsigned)ra.n_units);  // one block per band
+            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_class<kFP64, 16>), gs, bd, 0, s, tp, yr, gr, ra);
+            else hipLaunchKernelGGL((k_grid_class<kFP64, 8>), gs, bd, 0, s, tp, yr, gr, ra);
         }
     } else if constexpr (!kFP64) {  // w-plane kernels (FP32 path only)
         if (pl.n_items > 0) {
