@@ -947,6 +947,7 @@ __global__ __launch_bounds__(kThreads / kH, kFP64 ? 4 : 8) void k_grid_small(con
 // unit's band of the tile in LDS; the wavefronts of a block are independent
 // (no block barriers), so a block only groups them for the LDS allocation.
 struct RunArgs {
+    const int32_t *unit_order;  // class kernels: bands by decreasing taps (block -> band)
     const int4 *clsrec;
     const int32_t *unit_cls0;
     const int4 *runrec;
@@ -962,6 +963,7 @@ struct RunArgs {
 };
 
 constexpr int kRunWaves = 4;   // wavefronts (units) per block
+constexpr int kClassWaves = 4; // wavefronts per band in the class kernels
 constexpr int kRunChunk = 64;  // run records a grid wavefront stages in LDS at a time
 
 __device__ __forceinline__ void wave_fence() {
@@ -1210,12 +1212,14 @@ __device__ __forceinline__ void degrid_class_small(const typename Types<kFP64>::
     }
 }
 
-// A block serves one band: its kRunWaves wavefronts stage the band together
-// and then take every kRunWaves-th class each (classes are independent in
+// A block serves one band: its kClassWaves wavefronts stage the band together
+// and then take every kClassWaves-th class each (classes are independent in
 // degrid), so that a large band is not left to one wavefront at the end of
 // the launch (a wavefront streams at a small fraction of the chip's rate).
+// Blocks take the bands in decreasing order of taps, so that the launch ends
+// on small ones.
 template <bool kFP64, int kBR>
-__global__ __launch_bounds__(64 * kRunWaves) void k_degrid_class(const typename Types<kFP64>::C *__restrict__ taps,
+__global__ __launch_bounds__(64 * kClassWaves) void k_degrid_class(const typename Types<kFP64>::C *__restrict__ taps,
                                                                  const typename Types<kFP64>::C *__restrict__ grids,
                                                                  typename Types<kFP64>::C *dpart, RunArgs a) {
     using R = typename Types<kFP64>::R;
@@ -1223,18 +1227,18 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_degrid_class(const typename 
     __shared__ C sb[kBR * kTile];
     const int wid = wave_index();
     const int lane = threadIdx.x & 63;
-    const int64_t u = blockIdx.x;
+    const int64_t u = a.unit_order[blockIdx.x];
     const int c_first = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
     if (c_first >= c_end) return;  // uniform over the block
     constexpr int kNB = kTile / kBR;
     const int item = (int)(u / kNB), band = (int)(u % kNB);
     {
         const C *src = tile_origin(grids, a.item_key[item], a.tile_bits, a.G) + (int64_t)band * kBR * a.G;
-        for (int r = wid; r < kBR; r += kRunWaves) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
+        for (int r = wid; r < kBR; r += kClassWaves) sb[r * kTile + lane] = src[(int64_t)r * a.G + lane];
     }
     __syncthreads();
     const C *tu = taps + a.unit_tap0[u];
-    for (int c = c_first + wid; c < c_end; c += kRunWaves) {
+    for (int c = c_first + wid; c < c_end; c += kClassWaves) {
         const int4 cr = a.clsrec[c];
         const int nc = (cr.w >> 16) & 255, nrows = (cr.w >> 24) & 255, cell0 = cr.w & 0xFFFF;
         const int L = nc * nrows, run0 = cr.y, m = cr.z;
@@ -1337,19 +1341,19 @@ __device__ __forceinline__ typename Types<kFP64>::C grid_class_small(const typen
 }
 
 // Grid on run classes: a block serves one band; each of its wavefronts takes
-// every kRunWaves-th class and accumulates into its own copy of the band in
+// every kClassWaves-th class and accumulates into its own copy of the band in
 // LDS (a class's cells are distinct; classes go in program order), then the
 // block sums the copies in wavefront order (deterministic) and stores the band.
 template <bool kFP64, int kBR>
-__global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Types<kFP64>::C *__restrict__ taps,
-                                                               const typename Types<kFP64>::C *__restrict__ yr,
-                                                               typename Types<kFP64>::C *grids, RunArgs a) {
+__global__ __launch_bounds__(64 * kClassWaves) void k_grid_class(const typename Types<kFP64>::C *__restrict__ taps,
+                                                                 const typename Types<kFP64>::C *__restrict__ yr,
+                                                                 typename Types<kFP64>::C *grids, RunArgs a) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    __shared__ C s_band[kRunWaves][kBR * kTile];
+    __shared__ C s_band[kClassWaves][kBR * kTile];
     const int wid = wave_index();
     const int lane = threadIdx.x & 63;
-    const int64_t u = blockIdx.x;
+    const int64_t u = a.unit_order[blockIdx.x];
     const int c_first = a.unit_cls0[u], c_end = a.unit_cls0[u + 1];
     constexpr int kNB = kTile / kBR;
     const int item = (int)(u / kNB), band = (int)(u % kNB);
@@ -1363,7 +1367,7 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Ty
     for (int r = 0; r < kBR; ++r) sb[r * kTile + lane] = zero;
     wave_fence();
     const C *tu = taps + a.unit_tap0[u];
-    for (int c = c_first + wid; c < c_end; c += kRunWaves) {
+    for (int c = c_first + wid; c < c_end; c += kClassWaves) {
         const int4 cr = a.clsrec[c];
         const int nc = (cr.w >> 16) & 255, nrows = (cr.w >> 24) & 255, cell0 = cr.w & 0xFFFF;
         const int L = nc * nrows, run0 = cr.y, m = cr.z;
@@ -1439,10 +1443,10 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_grid_class(const typename Ty
     }
     dst += (int64_t)band * kBR * ld;
     __syncthreads();
-    for (int r = wid; r < kBR; r += kRunWaves) {
+    for (int r = wid; r < kBR; r += kClassWaves) {
         C v = s_band[0][r * kTile + lane];
 #pragma unroll
-        for (int w = 1; w < kRunWaves; ++w) {
+        for (int w = 1; w < kClassWaves; ++w) {
             const C t = s_band[w][r * kTile + lane];
             v.x += t.x;
             v.y += t.y;
@@ -1721,6 +1725,7 @@ static bool grid_on_runs(const Plan &pl) { return 2 * pl.long_taps > pl.total_ta
 RunArgs run_args(const wsp_ctx *c) {
     const Plan &pl = c->plan;
     RunArgs r{};
+    r.unit_order = pl.unit_order;
     r.clsrec = pl.clsrec;
     r.unit_cls0 = pl.unit_cls0;
     r.runrec = pl.runrec;
@@ -1807,9 +1812,9 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
                 if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_lanes<kFP64, 16>), gd, bd, 0, s, tp, gr, dp, ra);
                 else hipLaunchKernelGGL((k_degrid_lanes<kFP64, 8>), gd, bd, 0, s, tp, gr, dp, ra);
             } else {
-                const dim3 gs((unsigned)ra.n_units);  // one block per band
-                if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_class<kFP64, 16>), gs, bd, 0, s, tp, gr, dp, ra);
-                else hipLaunchKernelGGL((k_degrid_class<kFP64, 8>), gs, bd, 0, s, tp, gr, dp, ra);
+                const dim3 gs((unsigned)ra.n_units), bs(64 * kClassWaves);  // one block per band
+                if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_degrid_class<kFP64, 16>), gs, bs, 0, s, tp, gr, dp, ra);
+                else hipLaunchKernelGGL((k_degrid_class<kFP64, 8>), gs, bs, 0, s, tp, gr, dp, ra);
             }
         }
         // class kernels write run partials in layout order
@@ -1872,9 +1877,9 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
             C *yr = (C *)c->scratch_dpart;
             hipLaunchKernelGGL(k_prep_runs<kFP64>, dim3(blocks(pl.n_runs, 256)), dim3(256), 0, s, yw, pl.runrec,
                                pl.n_runs, yr);
-            const dim3 gs((unsigned)ra.n_units);  // one block per band
-            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_class<kFP64, 16>), gs, bd, 0, s, tp, yr, gr, ra);
-            else hipLaunchKernelGGL((k_grid_class<kFP64, 8>), gs, bd, 0, s, tp, yr, gr, ra);
+            const dim3 gs((unsigned)ra.n_units), bs(64 * kClassWaves);  // one block per band
+            if (pl.tile_band_rows == 16) hipLaunchKernelGGL((k_grid_class<kFP64, 16>), gs, bs, 0, s, tp, yr, gr, ra);
+            else hipLaunchKernelGGL((k_grid_class<kFP64, 8>), gs, bs, 0, s, tp, yr, gr, ra);
         }
     } else if constexpr (!kFP64) {  // w-plane kernels (FP32 path only)
         if (pl.n_items > 0) {

@@ -545,6 +545,15 @@ __global__ void k_class_records(const int32_t *__restrict__ cls_run0, const uint
     clsrec[c] = make_int4(rr.x, r0, r1 - r0, rr.y);
 }
 
+// Sort keys for the band order of the class kernels: the band's taps (to be
+// sorted in decreasing order) and its index.
+__global__ void k_unit_sizes(const int64_t *__restrict__ unit_tap0, int64_t U, int64_t *sz, int32_t *idx) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= U) return;
+    sz[u] = unit_tap0[u + 1] - unit_tap0[u];
+    idx[u] = (int32_t)u;
+}
+
 // Taps in classes whose shape has more than 64 taps.
 __global__ void k_long_taps(const int4 *__restrict__ clsrec, int64_t n_cls, unsigned long long *out) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -775,10 +784,10 @@ void free_sorted_plan(Plan &pl) {
     pl.ptw = nullptr;
     pl.n_pairs = 0;
     pl.table_len = 0;
-    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec,  pl.unit_run0, pl.unit_tap0,
-                     pl.run_lay,   pl.len16,   pl.suf,     pl.grp_tap,   pl.clsrec, pl.unit_cls0};
+    void *rptrs[] = {pl.run_first, pl.run_tap, pl.runrec,  pl.unit_run0, pl.unit_tap0,  pl.run_lay,
+                     pl.len16,     pl.suf,     pl.grp_tap, pl.clsrec,    pl.unit_cls0, pl.unit_order};
     for (void *q : rptrs) dfree(q);
-    pl.run_first = pl.unit_run0 = pl.run_lay = pl.unit_cls0 = nullptr;
+    pl.run_first = pl.unit_run0 = pl.run_lay = pl.unit_cls0 = pl.unit_order = nullptr;
     pl.clsrec = nullptr;
     pl.n_classes = 0;
     pl.long_taps = 0;
@@ -1364,6 +1373,28 @@ static hipError_t make_runs(Plan &pl, hipStream_t s) {
             WSP_RSTEP(hipMemsetAsync(pl.unit_cls0, 0, sizeof(int32_t) * (size_t)(U + 1), s));
         }
         WSP_RSTEP(hipGetLastError());
+        // bands in decreasing order of taps (a stable sort: ties keep band order)
+        WSP_RSTEP(dalloc(&pl.unit_order, U));
+        if (U > 0) {
+            int64_t *sz = nullptr;
+            int32_t *ord_in = nullptr;
+            e = dalloc(&sz, 2 * U);
+            if (e == hipSuccess) e = dalloc(&ord_in, U);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_unit_sizes, dim3(grid1d(U, 256)), dim3(256), 0, s, pl.unit_tap0, U, sz, ord_in);
+                need = 0;
+                e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, need, sz, sz + U, ord_in, pl.unit_order,
+                                                                 (int)U, 0, 40, s);
+            }
+            if (e == hipSuccess) e = scratch(need);
+            if (e == hipSuccess)
+                e = hipcub::DeviceRadixSort::SortPairsDescending(tmp, need, sz, sz + U, ord_in, pl.unit_order,
+                                                                 (int)U, 0, 40, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            dfree(sz);
+            dfree(ord_in);
+            WSP_RSTEP(e);
+        }
     }
     int64_t total = 0;
     WSP_RSTEP(hipMemcpyAsync(&total, start_lay + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -218,6 +218,7 @@ struct Plan {
     int4 *clsrec = nullptr;       // [n_classes] {first tap relative to its unit, first run (layout),
                                   // runs, cell0 | nc << 16 | nrows << 24}
     int32_t *unit_cls0 = nullptr; // [n_items * bands + 1] first class of each unit
+    int32_t *unit_order = nullptr;// [n_items * bands] units by decreasing taps (ties: by index)
     int32_t *unit_run0 = nullptr; // [n_items * bands + 1] first run (layout order) of each unit
     int64_t *unit_tap0 = nullptr; // [n_items * bands + 1] first tap of each unit
 };
