@@ -15,7 +15,8 @@
 // first pass (so the panel estimates add up to at most tol S), otherwise it
 // is bisected; rounds repeat until every panel passes or the panel cap is
 // reached.  Probes are evaluated in FP64 so the estimate is not swamped by
-// FP32 rounding.
+// FP32 rounding, one Gauss-Kronrod node per lane (16-lane groups, four
+// panels per pass), the probe sums reduced across each group.
 //
 // Phase 2 (taps).  Every tap is integrated with the 15-point Kronrod rule on
 // the final partition.  FP32 path: node values g(r) r e^{...} in FP64, cast to
@@ -173,45 +174,6 @@ __device__ __forceinline__ void node_value(double r, double weff, const Geom &g,
     *im = amp * sn;
 }
 
-// G7/K15 on panel [a, b] at the probe distances; returns the error estimate
-// and (if acc) adds the K15 values into sre/sim.
-__device__ float eval_panel_probes(double a, double b, double weff, double qstep, const Geom &g,
-                                   double *sre, double *sim, bool acc) {
-    double half = 0.5 * (b - a), mid = 0.5 * (a + b);
-    double kr[kProbes], ki[kProbes], gr[kProbes], gi[kProbes];
-#pragma unroll
-    for (int j = 0; j < kProbes; ++j) kr[j] = ki[j] = gr[j] = gi[j] = 0.0;
-    for (int n = 0; n < WSP_GK_N; ++n) {
-        double r = fma(half, wsp_gk_x[n], mid);
-        double are, aim;
-        node_value(r, weff, g, &are, &aim);
-        double wk = wsp_gk_wk[n], wg = wsp_gk_wg[n];
-#pragma unroll
-        for (int j = 0; j < kProbes; ++j) {
-            const double q = qstep * j;
-            const double x = kTwoPi * (r * q);
-            // 8 / x and sqrt(2 / (pi x)) for the Hankel branch (x >= 8 there)
-            const double J = x < 8.0 ? j0_small(x) : j0_fp64(r, q, 8.0 / x, sqrt(0.6366197723675814 / x));
-            double tr = are * J, ti = aim * J;
-            kr[j] = fma(wk, tr, kr[j]);
-            ki[j] = fma(wk, ti, ki[j]);
-            gr[j] = fma(wg, tr, gr[j]);
-            gi[j] = fma(wg, ti, gi[j]);
-        }
-    }
-    double err = 0.0;
-#pragma unroll
-    for (int j = 0; j < kProbes; ++j) {
-        double dr = kr[j] - gr[j], di = ki[j] - gi[j];
-        err = fmax(err, half * sqrt(dr * dr + di * di));
-        if (acc) {
-            sre[j] += half * kr[j];
-            sim[j] += half * ki[j];
-        }
-    }
-    return (float)err;
-}
-
 // Sum over each row of 16 lanes with DPP moves (no LDS): quad swaps, then the
 // half-row and row mirrors; every lane of the row ends with the row's sum.
 template <int kCtrl>
@@ -229,17 +191,24 @@ __device__ __forceinline__ double row_sum16(double v) {
     return v;
 }
 
-// The same G7/K15 estimates for the marked panels idx[0 .. ne), one
+// 1 / j and 1 / sqrt(j) for the probe distances q_j = j q_1: x_j = j x_1, so
+// the Hankel factors 8 / x and sqrt(2 / (pi x)) of every probe follow from
+// those of probe 1 (one division and one square root per node).
+__constant__ double kInvJ[kProbes] = {0.0, 1.0, 0.5, 1.0 / 3.0, 0.25, 0.2, 1.0 / 6.0, 1.0 / 7.0};
+__constant__ double kInvSqrtJ[kProbes] = {0.0, 1.0, 0.70710678118654752440, 0.57735026918962576451, 0.5,
+                                          0.44721359549995793928, 0.40824829046386301637,
+                                          0.37796447300922722721};
+
+// G7/K15 error estimates for the marked panels idx[0 .. ne), one
 // Gauss-Kronrod node per lane: 16-lane groups (15 nodes used) take 4 panels
-// per pass and sum their nodes across the group.  Used when a round has few
-// panels to evaluate, where one panel per lane would leave most lanes idle.
-// The estimate needs only K15 - G7, one sum per probe; the K15 values
-// themselves only when acc (the first round).  Panel idx[k]'s error goes to
-// errv[idx[k]]; with acc the K15 values are added into sre / sim of the
-// group's first lane.
+// per pass and sum their nodes across the group, so the per-probe sums live
+// across lanes rather than in one lane's registers.  The estimate needs
+// only K15 - G7, one sum per probe: max_j |K15_j - G7_j| over the probes.
+// Panel idx[k]'s error goes to errv[idx[k]].  With acc (the first round) the
+// K15 values are also added into acc[(group * kProbes + j) * 2 + {0, 1}]
+// (LDS; each group's first lane owns its entries).
 __device__ void eval_marked_grouped(const float *cur, const int *idx, int ne, double weff, double qstep,
-                                    const Geom &g, float *errv, double *sre, double *sim, bool acc,
-                                    int lane) {
+                                    const Geom &g, float *errv, double *acc, int lane) {
     const int grp = lane >> 4, nd = lane & 15;
     for (int k0 = 0; k0 < ne; k0 += kWave / 16) {
         const int k = k0 + grp;
@@ -251,50 +220,44 @@ __device__ void eval_marked_grouped(const float *cur, const int *idx, int ne, do
             b = (double)fabsf(cur[pi + 1]);
         }
         const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
-        double tr[kProbes], ti[kProbes];
-        double wk = 0.0, wg = 0.0;
-#pragma unroll
-        for (int j = 0; j < kProbes; ++j) tr[j] = ti[j] = 0.0;
+        // idle lanes keep r = 0 and zero weights: they add nothing
+        double r = 0.0, are = 0.0, aim = 0.0, wk = 0.0, wg = 0.0, inv1 = 0.0, amp1 = 0.0;
         if (k < ne && nd < WSP_GK_N) {
-            const double r = fma(half, wsp_gk_x[nd], mid);
-            double are, aim;
+            r = fma(half, wsp_gk_x[nd], mid);
             node_value(r, weff, g, &are, &aim);
             wk = wsp_gk_wk[nd];
             wg = wsp_gk_wg[nd];
-#pragma unroll
-            for (int j = 0; j < kProbes; ++j) {
-                const double q = qstep * j;
-                const double x = kTwoPi * (r * q);
-                const double J = x < 8.0 ? j0_small(x) : j0_fp64(r, q, 8.0 / x, sqrt(0.6366197723675814 / x));
-                tr[j] = are * J;
-                ti[j] = aim * J;
-            }
+            const double x1 = kTwoPi * (r * qstep);
+            inv1 = 8.0 / x1;
+            amp1 = sqrt(0.6366197723675814 / x1);
         }
         const double wd = wk - wg;
-        double err = 0.0;
-#pragma unroll
+        double e2 = 0.0;
+        // one probe at a time (a rolled loop): fewer live registers
+#pragma unroll 1
         for (int j = 0; j < kProbes; ++j) {
-            const double dr = row_sum16(wd * tr[j]), di = row_sum16(wd * ti[j]);
-            err = fmax(err, half * sqrt(dr * dr + di * di));
-        }
-        if (acc) {
-#pragma unroll
-            for (int j = 0; j < kProbes; ++j) {
-                const double kr = row_sum16(wk * tr[j]), ki = row_sum16(wk * ti[j]);
+            const double q = qstep * j;
+            const double x = kTwoPi * (r * q);
+            const double J = x < 8.0 ? j0_small(x) : j0_fp64(r, q, inv1 * kInvJ[j], amp1 * kInvSqrtJ[j]);
+            const double tr = are * J, ti = aim * J;
+            const double dr = row_sum16(wd * tr), di = row_sum16(wd * ti);
+            e2 = fmax(e2, dr * dr + di * di);
+            if (acc != nullptr) {
+                const double kr = row_sum16(wk * tr), ki = row_sum16(wk * ti);
                 if (k < ne && nd == 0) {
-                    sre[j] += half * kr;
-                    sim[j] += half * ki;
+                    acc[(grp * kProbes + j) * 2] += half * kr;
+                    acc[(grp * kProbes + j) * 2 + 1] += half * ki;
                 }
             }
         }
-        if (k < ne && nd == 0) errv[pi] = (float)err;
+        if (k < ne && nd == 0) errv[pi] = (float)(half * sqrt(e2));
     }
 }
 
 // Phase 1.  Returns the panel count; the partition ends up in *out (LDS), as
 // |bnd[0]| < |bnd[1]| < ... < |bnd[P]|.
-__device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, double weff, double qmax,
-                                  const BuildArgs &A, int lane, bool *capped) {
+__device__ int adaptive_partition(float *bA, float *bB, int *idx, double *acc, float **out, double weff,
+                                  double qmax, const BuildArgs &A, int lane, bool *capped) {
     const Geom &g = A.g;
     const double R = g.r_max;
     const double aw = fabs(weff);
@@ -325,9 +288,7 @@ __device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, d
     wave_sync();
     float *cur = bA, *oth = bB;
     const double qstep = qmax / (double)(kProbes - 1);
-    double sre[kProbes], sim[kProbes];
-#pragma unroll
-    for (int j = 0; j < kProbes; ++j) sre[j] = sim[j] = 0.0;
+    for (int k = lane; k < 2 * 4 * kProbes; k += kWave) acc[k] = 0.0;
     double thr = 0.0;
     *capped = false;
     constexpr int kChunks = kMaxPanels / kWave;
@@ -342,8 +303,10 @@ __device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, d
                 ne += __popcll(__ballot(i < P && signbit(cur[i])));
             }
         }
+        double *acc_r = round == 0 ? acc : nullptr;
+        // errors go through oth: few marked panels are listed and evaluated
+        // together, many chunk by chunk
         if (ne <= kWave) {
-            // few panels: list them, evaluate one node per lane, errors via oth
             int run = 0;
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
@@ -356,33 +319,38 @@ __device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, d
                 }
             }
             wave_sync();
-            eval_marked_grouped(cur, idx, ne, weff, qstep, g, oth, sre, sim, round == 0, lane);
+            eval_marked_grouped(cur, idx, ne, weff, qstep, g, oth, acc_r, lane);
             wave_sync();
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const int i = c * kWave + lane;
-                err[c] = (c * kWave < P && i < P && signbit(cur[i])) ? oth[i] : -1.0f;
-            }
-            wave_sync();  // oth is rewritten by the split below
         } else {
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                err[c] = -1.0f;
-                int i = c * kWave + lane;
-                if (c * kWave < P && i < P) {
-                    float fa = cur[i];
-                    if (signbit(fa)) {
-                        err[c] = eval_panel_probes((double)fabsf(fa), (double)fabsf(cur[i + 1]), weff,
-                                                   qstep, g, sre, sim, round == 0);
-                    }
-                }
+#pragma unroll 1
+            for (int c = 0; c * kWave < P; ++c) {
+                const int i = c * kWave + lane;
+                const bool mk = i < P && signbit(cur[i]);
+                const unsigned long long bal = __ballot(mk);
+                if (bal == 0ull) continue;
+                if (mk) idx[__popcll(bal & lanemask_lt(lane))] = i;
+                wave_sync();
+                eval_marked_grouped(cur, idx, __popcll(bal), weff, qstep, g, oth, acc_r, lane);
+                wave_sync();  // idx is rewritten by the next chunk
             }
         }
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const int i = c * kWave + lane;
+            err[c] = (c * kWave < P && i < P && signbit(cur[i])) ? oth[i] : -1.0f;
+        }
+        wave_sync();  // oth is rewritten by the split below
         if (round == 0) {
+            // S = max_j |K(q_j)| from the first pass over the whole interval
             double S = 0.0;
 #pragma unroll
             for (int j = 0; j < kProbes; ++j) {
-                double re = wave_sum(sre[j]), im = wave_sum(sim[j]);
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int gq = 0; gq < 4; ++gq) {
+                    re += acc[(gq * kProbes + j) * 2];
+                    im += acc[(gq * kProbes + j) * 2 + 1];
+                }
                 S = fmax(S, sqrt(re * re + im * im));
             }
             thr = A.tol * S / R;
@@ -445,11 +413,13 @@ __device__ int adaptive_partition(float *bA, float *bB, int *idx, float **out, d
 }
 
 // Phase 1 kernel: one wavefront per visibility of the batch; writes the
-// final partition (|boundaries|) and its panel count.
-__global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, int nb,
-                                                   float *part, int *npan) {
+// final partition (|boundaries|) and its panel count.  Register use is
+// capped for three wavefronts per SIMD (168 VGPRs, a few bytes of spill).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_partition(
+    BuildArgs A, int64_t batch0, int nb, float *part, int *npan) {
     __shared__ float s_bnd[kWavesPerBlock][2][kMaxPanels + 2];
     __shared__ int s_idx[kWavesPerBlock][kWave];
+    __shared__ double s_acc[kWavesPerBlock][2 * 4 * kProbes];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int i = blockIdx.x * kWavesPerBlock + wid;
@@ -458,7 +428,8 @@ __global__ __launch_bounds__(256) void k_partition(BuildArgs A, int64_t batch0, 
     const double weff = tg.weff, qmax = tg.ps.qmax;
     float *bnd = nullptr;
     bool capped = false;
-    int P = adaptive_partition(s_bnd[wid][0], s_bnd[wid][1], s_idx[wid], &bnd, weff, qmax, A, lane, &capped);
+    int P = adaptive_partition(s_bnd[wid][0], s_bnd[wid][1], s_idx[wid], s_acc[wid], &bnd, weff, qmax, A, lane,
+                               &capped);
     float *dst = part + (int64_t)i * (kMaxPanels + 2);
     for (int k = lane; k <= P; k += kWave) dst[k] = fabsf(bnd[k]);
     if (lane == 0) {

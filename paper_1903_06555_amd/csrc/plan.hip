@@ -140,15 +140,28 @@ __global__ void k_kmeans_assign(const double *__restrict__ w, int64_t m,
 __global__ void k_kmeans_reduce(const double *__restrict__ psum,
                                 const unsigned long long *__restrict__ pcnt, int nblk, int K,
                                 double *centres) {
-    int q = threadIdx.x;
-    if (q >= K) return;
-    double s = 0.0;
+    // one block per stack: strided partial sums, then a fixed-order tree
+    // (deterministic for a given nblk)
+    __shared__ double rs[kRedBlock];
+    __shared__ unsigned long long rc[kRedBlock];
+    const int q = blockIdx.x;
+    double sm = 0.0;
     unsigned long long c = 0;
-    for (int b = 0; b < nblk; ++b) {
-        s += psum[(int64_t)b * K + q];
+    for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
+        sm += psum[(int64_t)b * K + q];
         c += pcnt[(int64_t)b * K + q];
     }
-    centres[q] = c > 0 ? s / (double)c : 0.0;
+    rs[threadIdx.x] = sm;
+    rc[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = kRedBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            rs[threadIdx.x] += rs[threadIdx.x + st];
+            rc[threadIdx.x] += rc[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) centres[q] = rc[0] > 0 ? rs[0] / (double)rc[0] : 0.0;
 }
 
 // ------------------------------------------------------- support + keys ---
@@ -740,8 +753,7 @@ hipError_t kmeans_iteration(const Plan &pl, const double *d_centres, int K, doub
     WSP_TRY(dmalloc(&dnew, sizeof(double) * K));
     hipLaunchKernelGGL(k_kmeans_assign, dim3(nblk), dim3(kRedBlock), 0, s, pl.w, pl.m, d_centres,
                        K, pl.label, psum, pcnt);
-    hipLaunchKernelGGL(k_kmeans_reduce, dim3(1), dim3(64 * ((K + 63) / 64)), 0, s, psum, pcnt,
-                       nblk, K, dnew);
+    hipLaunchKernelGGL(k_kmeans_reduce, dim3(K), dim3(kRedBlock), 0, s, psum, pcnt, nblk, K, dnew);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h_new, dnew, sizeof(double) * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
