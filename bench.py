@@ -565,6 +565,7 @@ def run_operator(wl, precision: str, kernels: str, steps: int, warmup: int, m_ov
                   "tap_layout": {1: "runs", 2: "interleaved"}.get(int(st["tap_layout"]), "planes"),
                   "lanes_busy": (taps / (64 * int(st["group_steps"])) if int(st["group_steps"]) else None),
                   "classes": int(st["classes"]), "long_taps": int(st["long_taps"]),
+                  "fft": "lds" if int(st["fft_lds"]) else "library", "fft_rows": int(st["fft_rows"]),
                   "items": int(st["items"]),
                   "tiles": int(st["tiles"]), "split_tiles": int(st["split_tiles"]),
                   "touched_cells": int(st["touched_cells"]), "plan_bytes": int(st["plan_bytes"]),

@@ -231,6 +231,11 @@ typedef struct wsp_plan_info {
     int64_t long_taps;        /* taps in classes whose shape has more than 64 taps (when
                                  more than half the taps, grid streams runs instead
                                  of accumulating classes in registers)              */
+    int32_t fft_lds;          /* 1: F and F^dagger run as LDS-resident transforms fused
+                                 with the image-side steps (G a power of two in
+                                 [64, 8192]); 0: batched library passes             */
+    int32_t fft_rows;         /* grid rows per stack that F fills and F^dagger reads
+                                 (the rows holding work items, or G)                */
 } wsp_plan_info;
 
 /* Fill *info.  touched_cells is counted on the device (synchronises it).

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwsp.so")
-SOURCES = ["api.cpp", "plan.hip", "build.hip", "apply.hip"]
+SOURCES = ["api.cpp", "plan.hip", "build.hip", "apply.hip", "fft.hip"]
 ARCH = os.environ.get("WSP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -66,22 +66,28 @@ void destroy_row_plans(wsp_ctx *c) {
     if (c->fft_ujoin_made) hipfftDestroy(c->fft_ujoin);
     if (c->fft_uhi_made) hipfftDestroy(c->fft_uhi);
     c->fft_ulo_made = c->fft_ujoin_made = c->fft_uhi_made = false;
+    dfree(c->fft_tile_bits);
+    dfree(c->fft_tile_list);
+    c->fft_tile_bits = nullptr;
+    c->fft_tile_list = nullptr;
+    c->n_fft_tiles = 0;
     c->fft_work = c->fft_work_base;
     c->g.rows_lo = c->g.G;
     c->g.rows_hi = 0;
 }
 
 // The grid rows that hold work items (tile rows of the item keys), and
-// batched plans for the U passes over just those rows when they leave at
-// least a quarter of the grid out.
+// batched library plans for the U passes over just those rows when they
+// leave at least a quarter of the grid out; for the LDS transforms, the used
+// rows and the bitmap and list of used tiles instead.
 hipfftResult make_row_plans(wsp_ctx *c) {
     destroy_row_plans(c);
     const Plan &pl = c->plan;
     const int G = c->g.G, T = G / kTile, K = c->g.n_stacks;
-    if (pl.n_items == 0) return HIPFFT_SUCCESS;
+    if (pl.n_items == 0 && !c->fft_lds) return HIPFFT_SUCCESS;
     std::vector<uint32_t> keys((size_t)pl.n_items);
-    if (hipMemcpy(keys.data(), pl.item_key, sizeof(uint32_t) * keys.size(), hipMemcpyDeviceToHost) !=
-        hipSuccess)
+    if (pl.n_items > 0 && hipMemcpy(keys.data(), pl.item_key, sizeof(uint32_t) * keys.size(),
+                                    hipMemcpyDeviceToHost) != hipSuccess)
         return HIPFFT_EXEC_FAILED;
     const uint32_t tmask = (1u << pl.tile_bits) - 1;
     int lo_t = 0, hi_t = 0;
@@ -91,6 +97,27 @@ hipfftResult make_row_plans(wsp_ctx *c) {
         else hi_t = T - ty > hi_t ? T - ty : hi_t;
     }
     const int rows_lo = lo_t * kTile, rows_hi = hi_t * kTile;
+    if (c->fft_lds) {  // the LDS transforms take the used rows and tiles directly
+        std::vector<uint64_t> bits;
+        std::vector<uint32_t> list;
+        fft_lds_tile_sets(c->g, keys, pl.tile_bits, &bits, &list);
+        list.push_back(0u);  // never empty (the count excludes it)
+        if (dmalloc(&c->fft_tile_bits, sizeof(uint64_t) * bits.size()) != hipSuccess ||
+            dmalloc(&c->fft_tile_list, sizeof(uint32_t) * list.size()) != hipSuccess ||
+            hipMemcpy(c->fft_tile_bits, bits.data(), sizeof(uint64_t) * bits.size(), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(c->fft_tile_list, list.data(), sizeof(uint32_t) * list.size(), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            destroy_row_plans(c);
+            return HIPFFT_ALLOC_FAILED;
+        }
+        c->n_fft_tiles = (int)list.size() - 1;
+        if (rows_lo + rows_hi > 0 && rows_lo + rows_hi < G) {
+            c->g.rows_lo = rows_lo;
+            c->g.rows_hi = rows_hi;
+        }
+        return HIPFFT_SUCCESS;
+    }
     if (4 * (rows_lo + rows_hi) > 3 * G) return HIPFFT_SUCCESS;  // not worth it
     const hipfftType ty = c->p.precision == WSP_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C;
     int len[1] = {G};
@@ -154,7 +181,7 @@ wsp_status finish_plan_inner(wsp_ctx *c, hipStream_t s) {
     hipfftResult fr = make_row_plans(c);
     if (fr != HIPFFT_SUCCESS) {
         c->planned = false;
-        return fail(WSP_EHIP, "hipfftMakePlanMany (row bands) failed (" + std::to_string((int)fr) + ")");
+        return fail(WSP_EHIP, "transform set-up for the used grid rows failed (" + std::to_string((int)fr) + ")");
     }
     c->planned = true;
     c->bound = false;
@@ -170,6 +197,7 @@ size_t wsp::cplx_bytes(const wsp_ctx *c) { return c->p.precision == WSP_FP64 ? 1
 namespace {
 // the half-size transform buffer: K x N rows of G cells
 size_t half_bytes(const wsp_ctx *c) {
+    if (c->fft_lds) return fft_lds_scratch_bytes(c->g, c->p.precision == WSP_FP64);
     return (size_t)c->g.n_stacks * c->g.n * c->g.G * cplx_bytes(c);
 }
 // degrid partial sums: one per run (exact kernels) or per tile entry (w-plane kernels)
@@ -352,7 +380,18 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     c->p = p;
     c->g = g;
     c->device = p.device;
-    {
+    c->fft_lds = fft_lds_fits(g.G, g.n, p.precision == WSP_FP64, p.device);
+    if (c->fft_lds) {
+        e = dmalloc(&c->fft_tw, (p.precision == WSP_FP64 ? 16 : 8) * (size_t)g.G);
+        if (e == hipSuccess) e = fft_lds_twiddles(g.G, p.precision == WSP_FP64, c->fft_tw);
+        if (e != hipSuccess) {
+            dfree(c->fft_tw);
+            delete c;
+            return hip_fail(e, "twiddle table");
+        }
+        c->g.rows_lo = g.G;
+        c->g.rows_hi = 0;
+    } else {
         const hipfftType ty = p.precision == WSP_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C;
         int len[1] = {g.G};
         size_t wv = 0, wu = 0;
@@ -383,8 +422,9 @@ wsp_status wsp_create(const wsp_params *pp, wsp_ctx **out) {
     }
     e = dmalloc(&c->plan_centres, sizeof(double) * g.n_stacks);
     if (e != hipSuccess) {
-        hipfftDestroy(c->fft_v);
-        hipfftDestroy(c->fft_u);
+        if (c->fft_v_made) hipfftDestroy(c->fft_v);
+        if (c->fft_u_made) hipfftDestroy(c->fft_u);
+        dfree(c->fft_tw);
         delete c;
         return hip_fail(e, "hipMalloc centres");
     }
@@ -558,6 +598,8 @@ wsp_status wsp_plan_stats(wsp_ctx *c, wsp_plan_info *info) {
     info->group_steps = pl.interleaved ? pl.group_steps : 0;
     info->classes = pl.n_classes;
     info->long_taps = pl.long_taps;
+    info->fft_lds = c->fft_lds ? 1 : 0;
+    info->fft_rows = c->g.rows_lo + c->g.rows_hi;
     return WSP_OK;
 }
 
@@ -854,6 +896,7 @@ void wsp_destroy(wsp_ctx *c) {
     dfree(c->dde_u);
     dfree(c->dde_v);
     dfree(c->plan_centres);
+    dfree(c->fft_tw);
     if (c->fft_v_made) hipfftDestroy(c->fft_v);
     if (c->fft_u_made) hipfftDestroy(c->fft_u);
     destroy_row_plans(c);

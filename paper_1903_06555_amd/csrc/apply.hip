@@ -12,62 +12,12 @@
 #include <type_traits>
 
 #include "wsp_devmath.h"
+#include "wsp_image.h"
 #include "wsp_plane.h"
 
 namespace wsp {
 
 namespace {
-
-template <bool kFP64>
-struct Types;
-template <>
-struct Types<false> {
-    using R = float;
-    using C = float2;
-};
-template <>
-struct Types<true> {
-    using R = double;
-    using C = double2;
-};
-
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b) {
-    C o;
-    o.x = a.x * b.x - a.y * b.y;
-    o.y = a.x * b.y + a.y * b.x;
-    return o;
-}
-
-// Per-pixel factors of S~_k (Eq. 4): 1 / (g(r) n) and n - 1 at pixel (j, i),
-// r = rho du cycles per cell; the stack enters only through the phase
-// -wbar_k (n - 1) revolutions.
-__device__ __forceinline__ void pixel_factors(int j, int i, const Geom &g, double *amp, double *nm1) {
-    double l = (double)(i - g.n / 2) * g.dl;
-    double m = (double)(j - g.n / 2) * g.dl;
-    double rho2 = l * l + m * m;
-    *nm1 = n_minus_one(rho2);
-    double gv = taper_g(sqrt(rho2) * g.du, g);
-    *amp = 1.0 / (gv * (1.0 + *nm1));
-}
-
-template <bool kFP64>
-__device__ __forceinline__ void rev_sincos(double f, typename Types<kFP64>::R *sn,
-                                           typename Types<kFP64>::R *cs) {
-    if constexpr (kFP64) {
-        sincospi(2.0 * f, sn, cs);
-    } else {
-        sincos_rev((float)f, sn, cs);
-    }
-}
-
-// pixel index of grid row/column V (Z places pixel N/2 at index 0), or -1
-__device__ __forceinline__ int pixel_of(int V, const Geom &g) {
-    int h = g.n / 2;
-    if (V < h) return V + h;
-    if (V >= g.G - h) return V - g.G + h;
-    return -1;
-}
 
 // F is computed in two passes of batched 1-D transforms of length G, with the
 // data transposed in between, so that neither pass touches the zero padding
@@ -82,12 +32,6 @@ __device__ __forceinline__ int pixel_of(int V, const Geom &g) {
 // Each transposing kernel stages a 64 x 64 tile in LDS so that its reads and
 // writes are both coalesced.
 constexpr int kT = 64;
-
-// column U of the padded image holding pixel column i (Z places pixel N/2 at 0)
-__device__ __forceinline__ int padded_of(int i, const Geom &g) {
-    int U = i - g.n / 2;
-    return U < 0 ? U + g.G : U;
-}
 
 // S~_k and Z for all stacks, written as H.  Block: (V tile, pixel-column tile).
 template <bool kFP64>
@@ -1789,15 +1733,26 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
     using C = typename Types<kFP64>::C;
     const Geom &g = c->g;
     hipEvent_t ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_taper_half<kFP64>, dim3(g.G / kT, (g.n + kT - 1) / kT), dim3(256), 0, s,
-                       (const R *)image, (C *)c->scratch_half, d_centres, g);
-    stage_end(c, kStTaperPad, ev, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    ev = stage_begin(c, s);
-    e = fft_exec<C>(c, true, s);
-    stage_end(c, kStFftForward, ev, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (c->fft_lds) {
+        e = fft_lds_image_in<kFP64>(g, image, c->scratch_half, s);
+        stage_end(c, kStTaperPad, ev, s);
+        if (e != hipSuccess) return e;
+        ev = stage_begin(c, s);
+        e = fft_lds_forward<kFP64>(g, c->grids, c->scratch_half, c->fft_tw, c->fft_tile_bits, d_centres, s);
+        stage_end(c, kStFftForward, ev, s);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_taper_half<kFP64>, dim3(g.G / kT, (g.n + kT - 1) / kT), dim3(256), 0, s,
+                           (const R *)image, (C *)c->scratch_half, d_centres, g);
+        stage_end(c, kStTaperPad, ev, s);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        ev = stage_begin(c, s);
+        e = fft_exec<C>(c, true, s);
+        stage_end(c, kStFftForward, ev, s);
+        if (e != hipSuccess) return e;
+    }
     ApplyArgs a = make_args(c);
     const Plan &pl = c->plan;
     const C *tp = (const C *)c->taps;
@@ -1850,7 +1805,10 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     const Geom &g = c->g;
     const int64_t ncell = (int64_t)(g.rows_lo + g.rows_hi) * g.G * g.n_stacks;
     hipEvent_t ev = stage_begin(c, s);
-    hipLaunchKernelGGL(k_zero_rows<C>, dim3(blocks(ncell, 256)), dim3(256), 0, s, (C *)c->grids, g);
+    if (c->fft_lds)  // F^dagger reads only the used tiles
+        fft_lds_zero_tiles<kFP64>(g, c->grids, c->fft_tile_list, c->n_fft_tiles, c->plan.tile_bits, s);
+    else
+        hipLaunchKernelGGL(k_zero_rows<C>, dim3(blocks(ncell, 256)), dim3(256), 0, s, (C *)c->grids, g);
     stage_end(c, kStZero, ev, s);
     ApplyArgs a = make_args(c);
     const Plan &pl = c->plan;
@@ -1899,6 +1857,15 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ev = stage_begin(c, s);
+    if (c->fft_lds) {
+        e = fft_lds_inverse<kFP64>(g, c->grids, c->scratch_half, c->fft_tw, c->fft_tile_bits, s);
+        stage_end(c, kStFftInverse, ev, s);
+        if (e != hipSuccess) return e;
+        ev = stage_begin(c, s);
+        e = fft_lds_image_out<kFP64>(g, image, c->scratch_half, c->fft_tw, d_centres, s);
+        stage_end(c, kStCropUntaper, ev, s);
+        return e;
+    }
     e = fft_exec<C>(c, false, s);
     stage_end(c, kStFftInverse, ev, s);
     if (e != hipSuccess) return e;

@@ -313,6 +313,16 @@ struct wsp_ctx {
     bool fft_ulo_made = false, fft_ujoin_made = false, fft_uhi_made = false;
     size_t fft_work_base = 0;  // work area of fft_v and fft_u
     size_t fft_work = 0;
+    // LDS-resident transforms (fft.hip) instead of the library passes, when
+    // G is a power of two in [64, 8192] and a transform fits one workgroup's
+    // LDS; fft_tw holds the twiddles of their Stockham passes (< G entries)
+    bool fft_lds = false;
+    void *fft_tw = nullptr;
+    // the planned work items' grid tiles: a bitmap (one bit per 64 x 64 tile)
+    // and a list of keys (stack | ty | tx); LDS transforms only
+    uint64_t *fft_tile_bits = nullptr;
+    uint32_t *fft_tile_list = nullptr;
+    int n_fft_tiles = 0;
     wsp::Plan plan;
     bool planned = false;
     std::vector<double> centres;   // host copy of the stack centres
@@ -324,7 +334,7 @@ struct wsp_ctx {
     size_t grid_bytes = 0;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
-    void *scratch_half = nullptr;   // [K][N][G] half-size transform buffer (inside scratch)
+    void *scratch_half = nullptr;   // transform buffers: [K][N][G] (library passes) or the LDS transforms' (inside scratch)
     void *scratch_yw = nullptr;     // weighted adjoint input, sorted order (inside scratch)
     void *scratch_part = nullptr;   // partial tiles of shared grid tiles (inside scratch)
     void *scratch_dpart = nullptr;  // degrid partial sums, one per tile entry (inside scratch)
@@ -373,6 +383,26 @@ size_t static_scratch_bytes();
 
 // api.cpp: stage timing around one launch (no-ops when timing is off)
 hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);
+// LDS-resident F and F^dagger with the image-side steps fused (fft.hip)
+bool fft_lds_fits(int G, int n, bool fp64, int device);
+hipError_t fft_lds_twiddles(int G, bool fp64, void *dev);
+size_t fft_lds_scratch_bytes(const Geom &g, bool fp64);
+template <bool kFP64>
+hipError_t fft_lds_image_in(const Geom &g, const void *image, void *scratch, hipStream_t s);
+template <bool kFP64>
+hipError_t fft_lds_forward(const Geom &g, void *grids, void *scratch, const void *tw, const uint64_t *tiles,
+                           const double *centres, hipStream_t s);
+template <bool kFP64>
+hipError_t fft_lds_inverse(const Geom &g, const void *grids, void *scratch, const void *tw, const uint64_t *tiles,
+                           hipStream_t s);
+template <bool kFP64>
+hipError_t fft_lds_zero_tiles(const Geom &g, void *grids, const uint32_t *list, int n_tiles, int tile_bits,
+                              hipStream_t s);
+void fft_lds_tile_sets(const Geom &g, const std::vector<uint32_t> &keys, int tile_bits, std::vector<uint64_t> *bits,
+                       std::vector<uint32_t> *list);
+template <bool kFP64>
+hipError_t fft_lds_image_out(const Geom &g, void *image, void *scratch, const void *tw, const double *centres,
+                             hipStream_t s);
 void stage_end(wsp_ctx *c, int stage, hipEvent_t start, hipStream_t s);
 
 // apply.hip

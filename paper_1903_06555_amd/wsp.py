@@ -110,6 +110,8 @@ class wsp_plan_info(ctypes.Structure):
         ("group_steps", ctypes.c_int64),
         ("classes", ctypes.c_int64),
         ("long_taps", ctypes.c_int64),
+        ("fft_lds", ctypes.c_int32),
+        ("fft_rows", ctypes.c_int32),
     ]
 
 
