@@ -1739,7 +1739,8 @@ hipError_t degrid_t(wsp_ctx *c, const void *image, void *vis, const double *d_ce
         stage_end(c, kStTaperPad, ev, s);
         if (e != hipSuccess) return e;
         ev = stage_begin(c, s);
-        e = fft_lds_forward<kFP64>(g, c->grids, c->scratch_half, c->fft_tw, c->fft_tile_bits, d_centres, s);
+        e = fft_lds_forward<kFP64>(g, c->grids, c->scratch_half, c->fft_tw, c->fft_tile_bits, d_centres, 0,
+                                   g.n_stacks, s);
         stage_end(c, kStFftForward, ev, s);
         if (e != hipSuccess) return e;
     } else {
@@ -1858,7 +1859,7 @@ hipError_t grid_t(wsp_ctx *c, const void *vis, void *image, const double *d_cent
     if (e != hipSuccess) return e;
     ev = stage_begin(c, s);
     if (c->fft_lds) {
-        e = fft_lds_inverse<kFP64>(g, c->grids, c->scratch_half, c->fft_tw, c->fft_tile_bits, s);
+        e = fft_lds_inverse<kFP64>(g, c->grids, c->scratch_half, c->fft_tw, c->fft_tile_bits, 0, g.n_stacks, s);
         stage_end(c, kStFftInverse, ev, s);
         if (e != hipSuccess) return e;
         ev = stage_begin(c, s);

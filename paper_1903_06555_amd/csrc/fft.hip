@@ -32,6 +32,7 @@ namespace {
 
 constexpr int kPerThread = 16;  // points per thread (radix-16 passes)
 constexpr int kPix = 8;         // pixels per thread along a column (N <= G / 2)
+constexpr int kURows = 4;       // grid rows per block of the forward U pass
 constexpr int kTT = 64;         // transpose tile
 
 // LDS slot of point i: one pad slot after every 16 points, so that the
@@ -224,14 +225,15 @@ __device__ __forceinline__ int used_row(int rr, const Geom &g) {
     return rr < g.rows_lo ? rr : g.G - g.rows_hi + (rr - g.rows_lo);
 }
 
-// Forward, first half.  Block: pixel column i.  For every stack k,
+// Forward, first half.  Block: pixel column i.  For every stack k of [k0, k1),
 // sm[V] = S~_k Z x along column i (zero where Z pads), transformed along V;
 // the used rows go to hp[k][i][rr].  Pixel j of the column is thread
 // j mod T's (q = j / T < 8, as N <= G / 2).
 template <bool kFP64, int kLog>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_fwd(
     const typename Types<kFP64>::R *__restrict__ imageT, typename Types<kFP64>::C *__restrict__ hp,
-    const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used) {
+    const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used, int k0,
+    int k1) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     constexpr int G = 1 << kLog, T = G / kPerThread;
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_fwd(
     C zero;
     zero.x = 0;
     zero.y = 0;
-    for (int k = 0; k < g.n_stacks; ++k) {
+    for (int k = k0; k < k1; ++k) {
         const double ck = centres[k];
 #pragma unroll
         for (int q = 0; q < kPix; ++q) {
@@ -278,67 +280,104 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_fwd(
     }
 }
 
-// Forward, second half.  Block: (used-row slot rr, stack k).  Row V(rr) of
-// the padded transform, from tp[k][rr][i] at the pixel columns (zero where
-// Z pads), transformed along U into the grid.
-template <bool kFP64, int kLog>
-__global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_fwd(
-    const typename Types<kFP64>::C *__restrict__ tp, typename Types<kFP64>::C *__restrict__ grids,
-    const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used) {
-    using C = typename Types<kFP64>::C;
-    constexpr int G = 1 << kLog, T = G / kPerThread;
-    __shared__ C sm[G + G / 16];
-    const int rr = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
-    const int n = g.n, h = n / 2;
-    const C *src = tp + ((int64_t)k * n_used + rr) * n;
-    for (int i = tid; i < n; i += T) sm[lds_pos(padded_of(i, g))] = src[i];
-    C zero;
-    zero.x = 0;
-    zero.y = 0;
-    for (int U = h + tid; U < G - h; U += T) sm[lds_pos(U)] = zero;
-    __syncthreads();
-    lds_fft<kLog, false>(sm, tw, tid);
-    const int V = used_row(rr, g);
-    C *dst = grids + ((int64_t)k * G + V) * G;
-    const TileRow<G> trow(tiles + ((int64_t)k * (G / kTile) + V / kTile) * kTileWords<G>);
+// The kPix pixel values of one row of n that thread tid holds (i = tid + q T).
+template <int T, typename C>
+__device__ __forceinline__ void fetch_pixels(C (&pre)[kPix], const C *__restrict__ src, int n, int tid) {
 #pragma unroll
-    for (int q = 0; q < kPerThread; ++q) {
-        const int U = tid + q * T;
-        if (trow.used(U)) dst[U] = sm[lds_pos(U)];
+    for (int q = 0; q < kPix; ++q) {
+        const int i = tid + q * T;
+        pre[q].x = 0;
+        pre[q].y = 0;
+        if (i < n) pre[q] = src[i];
     }
 }
 
-// Inverse, first half.  Block: (used-row slot rr, stack k).  Grid row V(rr)
-// transformed back along U; the N pixel columns go to tp[k][rr][i].
-template <bool kFP64, int kLog>
-__global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
-    const typename Types<kFP64>::C *__restrict__ grids, typename Types<kFP64>::C *__restrict__ tp,
-    const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used) {
-    using C = typename Types<kFP64>::C;
-    constexpr int G = 1 << kLog, T = G / kPerThread;
-    __shared__ C sm[G + G / 16];
-    const int rr = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
-    const int n = g.n;
-    const int V = used_row(rr, g);
+// The kPerThread cells U = tid + q T of grid row V of stack k: its used
+// tiles' values, zero elsewhere.
+template <int G, typename C>
+__device__ __forceinline__ void fetch_row(C (&pre)[kPerThread], const C *__restrict__ grids,
+                                          const uint64_t *__restrict__ tiles, int k, int V, int tid) {
+    constexpr int T = G / kPerThread;
     const C *src = grids + ((int64_t)k * G + V) * G;
     const TileRow<G> trow(tiles + ((int64_t)k * (G / kTile) + V / kTile) * kTileWords<G>);
-    C zero;
-    zero.x = 0;
-    zero.y = 0;
-    // all loads in flight before the LDS stores
-    C v[kPerThread];
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
         const int U = tid + q * T;
-        v[q] = zero;
-        if (trow.used(U)) v[q] = src[U];
+        pre[q].x = 0;
+        pre[q].y = 0;
+        if (trow.used(U)) pre[q] = src[U];
     }
+}
+
+// Forward, second half.  Block: kURows used-row slots rr of stack k.  Row
+// V(rr) of the padded transform, from tp[k][rr][i] at the pixel columns
+// (zero where Z pads), transformed along U into the used tiles of the grid.
+// The next row's inputs are loaded while the current row is transformed.
+template <bool kFP64, int kLog>
+__global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_fwd(
+    const typename Types<kFP64>::C *__restrict__ tp, typename Types<kFP64>::C *__restrict__ grids,
+    const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used,
+    int k0) {
+    using C = typename Types<kFP64>::C;
+    constexpr int G = 1 << kLog, T = G / kPerThread;
+    __shared__ C sm[G + G / 16];
+    const int k = k0 + (int)blockIdx.y, tid = threadIdx.x;
+    const int n = g.n, h = n / 2;
+    const int rr0 = blockIdx.x * kURows;
+    const int rr_end = rr0 + kURows < n_used ? rr0 + kURows : n_used;
+    C zero;
+    zero.x = 0;
+    zero.y = 0;
+    C pre[kPix];
+    fetch_pixels<T>(pre, tp + ((int64_t)k * n_used + rr0) * n, n, tid);
+    for (int rr = rr0; rr < rr_end; ++rr) {
+        const int t = opaque(tid);
+#pragma unroll
+        for (int q = 0; q < kPix; ++q) {
+            const int i = t + q * T;
+            if (i < n) sm[lds_pos(padded_of(i, g))] = pre[q];
+        }
+        for (int U = h + t; U < G - h; U += T) sm[lds_pos(U)] = zero;
+        if (rr + 1 < rr_end) fetch_pixels<T>(pre, tp + ((int64_t)k * n_used + rr + 1) * n, n, tid);
+        __syncthreads();
+        lds_fft<kLog, false>(sm, tw, t);
+        const int V = used_row(rr, g);
+        C *dst = grids + ((int64_t)k * G + V) * G;
+        const TileRow<G> trow(tiles + ((int64_t)k * (G / kTile) + V / kTile) * kTileWords<G>);
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+            const int U = t + q * T;
+            if (trow.used(U)) dst[U] = sm[lds_pos(U)];
+        }
+        __syncthreads();  // sm is refilled for the next row
+    }
+}
+
+// Inverse, first half.  Block: used-row slot rr of stack k.  Grid row V(rr)
+// (its used tiles; zero elsewhere) transformed back along U; the N pixel
+// columns go to tp[k][rr][i].
+template <bool kFP64, int kLog>
+__global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
+    const typename Types<kFP64>::C *__restrict__ grids, typename Types<kFP64>::C *__restrict__ tp,
+    const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used,
+    int k0) {
+    using C = typename Types<kFP64>::C;
+    constexpr int G = 1 << kLog, T = G / kPerThread;
+    __shared__ C sm[G + G / 16];
+    const int rr = blockIdx.x, k = k0 + (int)blockIdx.y, tid = threadIdx.x;
+    const int n = g.n;
+    C v[kPerThread];  // all loads in flight before the LDS stores
+    fetch_row<G>(v, grids, tiles, k, used_row(rr, g), tid);
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) sm[lds_pos(tid + q * T)] = v[q];
     __syncthreads();
     lds_fft<kLog, true>(sm, tw, tid);
     C *dst = tp + ((int64_t)k * n_used + rr) * n;
-    for (int i = tid; i < n; i += T) dst[i] = sm[lds_pos(padded_of(i, g))];
+#pragma unroll
+    for (int q = 0; q < kPix; ++q) {
+        const int i = tid + q * T;
+        if (i < n) dst[i] = sm[lds_pos(padded_of(i, g))];
+    }
 }
 
 // Inverse, second half.  Block: pixel column i.  For every stack k, the
@@ -370,12 +409,23 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
     C zero;
     zero.x = 0;
     zero.y = 0;
+    // the first kPix T used rows of the next stack's column are loaded while
+    // the current stack is transformed
+    C pre[kPix];
+    fetch_pixels<T>(pre, hp + (int64_t)i * n_used, n_used, tid);
     for (int k = 0; k < g.n_stacks; ++k) {
+        const int t = opaque(tid);
         const C *src = hp + ((int64_t)k * n + i) * n_used;
-        for (int rr = tid; rr < n_used; rr += T) sm[lds_pos(used_row(rr, g))] = src[rr];
-        for (int V = g.rows_lo + tid; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
+#pragma unroll
+        for (int q = 0; q < kPix; ++q) {
+            const int rr = t + q * T;
+            if (rr < n_used) sm[lds_pos(used_row(rr, g))] = pre[q];
+        }
+        for (int rr = t + kPix * T; rr < n_used; rr += T) sm[lds_pos(used_row(rr, g))] = src[rr];
+        for (int V = g.rows_lo + t; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
+        if (k + 1 < g.n_stacks) fetch_pixels<T>(pre, hp + ((int64_t)(k + 1) * n + i) * n_used, n_used, tid);
         __syncthreads();
-        lds_fft<kLog, true>(sm, tw, opaque(tid));
+        lds_fft<kLog, true>(sm, tw, t);
         const double ck = centres[k];
 #pragma unroll
         for (int q = 0; q < kPix; ++q) {
@@ -384,7 +434,7 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
                 R sn, cs;
                 rev_sincos<kFP64>(reduce_rev(-ck * nm[q]), &sn, &cs);
                 const C z = sm[lds_pos(padded_of(j, g))];
-                // Re(z conj(s_k)) with s_k = amp e^{2 pi i rev}
+                // Re(z conj(s_k)) with s_k = amp e^{2 pi i rev}; amp after the sum
                 acc[q] += (double)(z.x * cs + z.y * sn);
             }
         }
@@ -483,14 +533,14 @@ hipError_t fft_lds_twiddles(int G, bool fp64, void *dev) {
     return hipMemcpy(dev, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice);
 }
 
-// Scratch of the LDS transforms: hp [K][N][n_used], then tp [K][n_used][N]
-// (the transposed image shares tp's space).
+// Scratch of the LDS transforms: hp [K][N][n_used], tp [K][n_used][N], then
+// the transposed image imageT [N][N] (the forward's input, the adjoint's
+// output).
 size_t fft_lds_scratch_bytes(const Geom &g, bool fp64) {
     const size_t cb = fp64 ? 16 : 8, rb = fp64 ? 8 : 4;
     const size_t used = (size_t)(g.rows_lo + g.rows_hi);
-    const size_t half = (size_t)g.n_stacks * g.n * used * cb;
-    const size_t img = (size_t)g.n * g.n * rb;
-    return ((half + 255) & ~(size_t)255) + (half > img ? half : img);
+    const size_t half = ((size_t)g.n_stacks * g.n * used * cb + 255) & ~(size_t)255;
+    return 2 * half + (size_t)g.n * g.n * rb;
 }
 
 namespace {
@@ -504,28 +554,15 @@ struct LdsBuffers {
 template <bool kFP64>
 LdsBuffers<kFP64> lds_buffers(const Geom &g, void *scratch) {
     using C = typename Types<kFP64>::C;
-    const size_t half = (size_t)g.n_stacks * g.n * (g.rows_lo + g.rows_hi) * sizeof(C);
+    const size_t half = ((size_t)g.n_stacks * g.n * (g.rows_lo + g.rows_hi) * sizeof(C) + 255) & ~(size_t)255;
     LdsBuffers<kFP64> b;
     b.hp = (C *)scratch;
-    b.tp = (C *)((char *)scratch + ((half + 255) & ~(size_t)255));
-    b.imageT = (typename Types<kFP64>::R *)b.tp;
+    b.tp = (C *)((char *)scratch + half);
+    b.imageT = (typename Types<kFP64>::R *)((char *)scratch + 2 * half);
     return b;
 }
 
-}  // namespace
-
-// Forward, image side: the image transposed (pixel columns contiguous).
-template <bool kFP64>
-hipError_t fft_lds_image_in(const Geom &g, const void *image, void *scratch, hipStream_t s) {
-    using R = typename Types<kFP64>::R;
-    const LdsBuffers<kFP64> b = lds_buffers<kFP64>(g, scratch);
-    transpose_batch<R>((const R *)image, b.imageT, g.n, g.n, 1, s);
-    return hipGetLastError();
-}
-
-namespace {
-
-// Launch F(kLog) with the grid size as a template constant.
+// Launch F<kLog>::run with the grid size as a template constant.
 template <template <int> class F, typename... A>
 void by_size(int G, A... args) {
     switch (G) {
@@ -548,24 +585,27 @@ struct Launch {
     template <int kLog>
     struct Forward {
         static void run(const Geom &g, C *grids, LdsBuffers<kFP64> b, const C *tw, const uint64_t *tiles,
-                        const double *centres, hipStream_t s) {
-            const int used = g.rows_lo + g.rows_hi;
+                        const double *centres, int k0, int k1, hipStream_t s) {
+            const int used = g.rows_lo + g.rows_hi, nk = k1 - k0;
             const dim3 bd(1u << (kLog - 4));
             hipLaunchKernelGGL((k_fft_v_fwd<kFP64, kLog>), dim3((unsigned)g.n), bd, 0, s, (const R *)b.imageT,
-                               b.hp, tw, centres, g, used);
-            transpose_batch<C>(b.hp, b.tp, g.n, used, g.n_stacks, s);
-            hipLaunchKernelGGL((k_fft_u_fwd<kFP64, kLog>), dim3((unsigned)used, (unsigned)g.n_stacks), bd, 0, s,
-                               (const C *)b.tp, grids, tw, tiles, g, used);
+                               b.hp, tw, centres, g, used, k0, k1);
+            const int64_t off = (int64_t)k0 * g.n * used;
+            transpose_batch<C>(b.hp + off, b.tp + off, g.n, used, nk, s);
+            const dim3 gu((unsigned)((used + kURows - 1) / kURows), (unsigned)nk);
+            hipLaunchKernelGGL((k_fft_u_fwd<kFP64, kLog>), gu, bd, 0, s, (const C *)b.tp, grids, tw, tiles, g,
+                               used, k0);
         }
     };
     template <int kLog>
     struct Inverse {
         static void run(const Geom &g, const C *grids, LdsBuffers<kFP64> b, const C *tw, const uint64_t *tiles,
-                        hipStream_t s) {
-            const int used = g.rows_lo + g.rows_hi;
-            hipLaunchKernelGGL((k_fft_u_inv<kFP64, kLog>), dim3((unsigned)used, (unsigned)g.n_stacks),
-                               dim3(1u << (kLog - 4)), 0, s, grids, b.tp, tw, tiles, g, used);
-            transpose_batch<C>(b.tp, b.hp, used, g.n, g.n_stacks, s);
+                        int k0, int k1, hipStream_t s) {
+            const int used = g.rows_lo + g.rows_hi, nk = k1 - k0;
+            hipLaunchKernelGGL((k_fft_u_inv<kFP64, kLog>), dim3((unsigned)used, (unsigned)nk),
+                               dim3(1u << (kLog - 4)), 0, s, grids, b.tp, tw, tiles, g, used, k0);
+            const int64_t off = (int64_t)k0 * g.n * used;
+            transpose_batch<C>(b.tp + off, b.hp + off, used, g.n, nk, s);
         }
     };
     template <int kLog>
@@ -582,23 +622,45 @@ struct Launch {
 
 }  // namespace
 
-// Forward: S~_k, Z and F of every stack into the used rows of the grids.
+// Forward, image side: the image transposed (pixel columns contiguous).
 template <bool kFP64>
-hipError_t fft_lds_forward(const Geom &g, void *grids, void *scratch, const void *tw, const uint64_t *tiles,
-                           const double *centres, hipStream_t s) {
-    using C = typename Types<kFP64>::C;
-    by_size<Launch<kFP64>::template Forward>(g.G, g, (C *)grids, lds_buffers<kFP64>(g, scratch), (const C *)tw,
-                                             tiles, centres, s);
+hipError_t fft_lds_image_in(const Geom &g, const void *image, void *scratch, hipStream_t s) {
+    using R = typename Types<kFP64>::R;
+    const LdsBuffers<kFP64> b = lds_buffers<kFP64>(g, scratch);
+    transpose_batch<R>((const R *)image, b.imageT, g.n, g.n, 1, s);
     return hipGetLastError();
 }
 
-// Inverse, grid side: F^dagger along U of the used rows, transposed.
+// Forward: S~_k, Z and F of stacks [k0, k1) into the used tiles of the grids.
+template <bool kFP64>
+hipError_t fft_lds_forward(const Geom &g, void *grids, void *scratch, const void *tw, const uint64_t *tiles,
+                           const double *centres, int k0, int k1, hipStream_t s) {
+    using C = typename Types<kFP64>::C;
+    by_size<Launch<kFP64>::template Forward>(g.G, g, (C *)grids, lds_buffers<kFP64>(g, scratch), (const C *)tw,
+                                             tiles, centres, k0, k1, s);
+    return hipGetLastError();
+}
+
+// Inverse, grid side: F^dagger along U of the used rows of stacks [k0, k1),
+// transposed.
 template <bool kFP64>
 hipError_t fft_lds_inverse(const Geom &g, const void *grids, void *scratch, const void *tw, const uint64_t *tiles,
-                           hipStream_t s) {
+                           int k0, int k1, hipStream_t s) {
     using C = typename Types<kFP64>::C;
     by_size<Launch<kFP64>::template Inverse>(g.G, g, (const C *)grids, lds_buffers<kFP64>(g, scratch),
-                                             (const C *)tw, tiles, s);
+                                             (const C *)tw, tiles, k0, k1, s);
+    return hipGetLastError();
+}
+
+// Inverse, image side: F^dagger along V, Z^dagger, S~_k^dagger, Re and the
+// sum over stacks, into the image.
+template <bool kFP64>
+hipError_t fft_lds_image_out(const Geom &g, void *image, void *scratch, const void *tw, const double *centres,
+                             hipStream_t s) {
+    using R = typename Types<kFP64>::R;
+    using C = typename Types<kFP64>::C;
+    by_size<Launch<kFP64>::template ImageOut>(g.G, g, (R *)image, lds_buffers<kFP64>(g, scratch), (const C *)tw,
+                                              centres, s);
     return hipGetLastError();
 }
 
@@ -629,27 +691,15 @@ void fft_lds_tile_sets(const Geom &g, const std::vector<uint32_t> &keys, int til
     }
 }
 
-// Inverse, image side: F^dagger along V, Z^dagger, S~_k^dagger, Re and the
-// sum over stacks, into the image.
-template <bool kFP64>
-hipError_t fft_lds_image_out(const Geom &g, void *image, void *scratch, const void *tw, const double *centres,
-                             hipStream_t s) {
-    using R = typename Types<kFP64>::R;
-    using C = typename Types<kFP64>::C;
-    by_size<Launch<kFP64>::template ImageOut>(g.G, g, (R *)image, lds_buffers<kFP64>(g, scratch),
-                                              (const C *)tw, centres, s);
-    return hipGetLastError();
-}
-
-#define WSP_FFT_LDS_INST(F64)                                                                                    \
-    template hipError_t fft_lds_image_in<F64>(const Geom &, const void *, void *, hipStream_t);                 \
-    template hipError_t fft_lds_forward<F64>(const Geom &, void *, void *, const void *, const uint64_t *,       \
-                                             const double *, hipStream_t);                                      \
-    template hipError_t fft_lds_inverse<F64>(const Geom &, const void *, void *, const void *, const uint64_t *, \
-                                             hipStream_t);                                                      \
-    template hipError_t fft_lds_zero_tiles<F64>(const Geom &, void *, const uint32_t *, int, int, hipStream_t);  \
-    template hipError_t fft_lds_image_out<F64>(const Geom &, void *, void *, const void *, const double *,      \
-                                               hipStream_t);
+#define WSP_FFT_LDS_INST(F64)                                                                                      \
+    template hipError_t fft_lds_image_in<F64>(const Geom &, const void *, void *, hipStream_t);                   \
+    template hipError_t fft_lds_forward<F64>(const Geom &, void *, void *, const void *, const uint64_t *,         \
+                                             const double *, int, int, hipStream_t);                              \
+    template hipError_t fft_lds_inverse<F64>(const Geom &, const void *, void *, const void *, const uint64_t *,   \
+                                             int, int, hipStream_t);                                              \
+    template hipError_t fft_lds_image_out<F64>(const Geom &, void *, void *, const void *, const double *,        \
+                                               hipStream_t);                                                      \
+    template hipError_t fft_lds_zero_tiles<F64>(const Geom &, void *, const uint32_t *, int, int, hipStream_t);
 WSP_FFT_LDS_INST(false)
 WSP_FFT_LDS_INST(true)
 #undef WSP_FFT_LDS_INST

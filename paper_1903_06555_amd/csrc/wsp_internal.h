@@ -383,7 +383,8 @@ size_t static_scratch_bytes();
 
 // api.cpp: stage timing around one launch (no-ops when timing is off)
 hipEvent_t stage_begin(wsp_ctx *c, hipStream_t s);
-// LDS-resident F and F^dagger with the image-side steps fused (fft.hip)
+// LDS-resident F and F^dagger with the image-side steps fused (fft.hip); the
+// forward and the U passes take a range of stacks [k0, k1)
 bool fft_lds_fits(int G, int n, bool fp64, int device);
 hipError_t fft_lds_twiddles(int G, bool fp64, void *dev);
 size_t fft_lds_scratch_bytes(const Geom &g, bool fp64);
@@ -391,10 +392,11 @@ template <bool kFP64>
 hipError_t fft_lds_image_in(const Geom &g, const void *image, void *scratch, hipStream_t s);
 template <bool kFP64>
 hipError_t fft_lds_forward(const Geom &g, void *grids, void *scratch, const void *tw, const uint64_t *tiles,
-                           const double *centres, hipStream_t s);
+                           const double *centres, int k0, int k1, hipStream_t s);
 template <bool kFP64>
 hipError_t fft_lds_inverse(const Geom &g, const void *grids, void *scratch, const void *tw, const uint64_t *tiles,
-                           hipStream_t s);
+                           int k0, int k1, hipStream_t s);
+
 template <bool kFP64>
 hipError_t fft_lds_zero_tiles(const Geom &g, void *grids, const uint32_t *list, int n_tiles, int tile_bits,
                               hipStream_t s);
