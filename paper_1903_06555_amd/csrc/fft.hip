@@ -467,22 +467,33 @@ __global__ __launch_bounds__(256) void k_zero_tiles(C *grids, const uint32_t *__
 }
 
 // dst[b][c][r] = src[b][r][c] for a batch of rows x cols matrices (64 x 64
-// tiles through LDS: coalesced reads and writes).  Block: (column tile, row
-// tile, batch).
+// tiles through LDS: coalesced reads and writes; each thread's 16 loads are
+// all issued before the LDS stores).  Block: (column tile, row tile, batch).
 template <typename E>
 __global__ __launch_bounds__(256) void k_transpose_batch(const E *__restrict__ src, E *__restrict__ dst,
                                                          int rows, int cols) {
+    constexpr int kPer = kTT * kTT / 256;
     __shared__ E s_t[kTT][kTT + 1];
     const int c0 = blockIdx.x * kTT, r0 = blockIdx.y * kTT;
     const int64_t off = (int64_t)blockIdx.z * rows * cols;
-    for (int e = threadIdx.x; e < kTT * kTT; e += 256) {
-        const int r = e / kTT, c = e % kTT;
-        if (r0 + r < rows && c0 + c < cols) s_t[r][c] = src[off + (int64_t)(r0 + r) * cols + c0 + c];
+    const int c = threadIdx.x % kTT, rq = threadIdx.x / kTT;  // rows rq, rq + 4, ...
+    E v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int r = rq + 4 * q;
+        v[q] = E{};
+        if (r0 + r < rows && c0 + c < cols) v[q] = src[off + (int64_t)(r0 + r) * cols + c0 + c];
     }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) s_t[rq + 4 * q][c] = v[q];
     __syncthreads();
-    for (int e = threadIdx.x; e < kTT * kTT; e += 256) {
-        const int c = e / kTT, r = e % kTT;
-        if (r0 + r < rows && c0 + c < cols) dst[off + (int64_t)(c0 + c) * rows + r0 + r] = s_t[r][c];
+    // now c indexes rows of the source (contiguous in dst), rq + 4 q its columns
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) v[q] = s_t[c][rq + 4 * q];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int cc = rq + 4 * q;
+        if (r0 + c < rows && c0 + cc < cols) dst[off + (int64_t)(c0 + cc) * rows + r0 + c] = v[q];
     }
 }
 
