@@ -177,6 +177,9 @@ struct ApplyArgs {
     const int32_t *perm, *jp, *u0w, *v0w, *stack;
     const double *wt;
     const uint8_t *sflag;
+    const int32_t *iperm;      // caller -> sorted
+    const double *wt_in;       // caller order
+    const uint8_t *flag;       // caller order
     const int64_t *tap_off;
     int64_t m;
     Geom g;
@@ -190,25 +193,27 @@ __device__ __forceinline__ R wave_sum_r(R x) {
 
 // W_k and Eq. (8) on the adjoint's input: yw[p] = W_p (conj) y[perm[p]] in
 // sorted order.  rot = 1 takes -i y instead (the Stokes U half of the
-// polarised adjoint, Eq. (9)).
+// polarised adjoint, Eq. (9)).  One thread per caller-order visibility:
+// its reads are coalesced and only the store is scattered (a gather in
+// sorted order would fetch a cache line per 8-byte visibility).
 template <bool kFP64>
 __global__ void k_prep_vis(const typename Types<kFP64>::C *__restrict__ vis,
                            typename Types<kFP64>::C *yw, ApplyArgs a, int rot) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.m) return;
-    C y = vis[a.perm[p]];
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.m) return;
+    C y = vis[q];
     if (rot) {
         const R re = y.x;
         y.x = y.y;
         y.y = -re;
     }
-    R w = (R)a.wt[p];
+    R w = (R)a.wt_in[q];
     C o;
     o.x = y.x * w;
-    o.y = (a.sflag[p] ? -y.y : y.y) * w;
-    yw[p] = o;
+    o.y = (a.flag[q] ? -y.y : y.y) * w;
+    yw[a.iperm[q]] = o;
 }
 
 struct TileArgs {
@@ -1596,6 +1601,9 @@ ApplyArgs make_args(const wsp_ctx *c) {
     a.stack = pl.stack;
     a.wt = pl.wt;
     a.sflag = pl.sflag;
+    a.iperm = pl.iperm;
+    a.wt_in = pl.wt_in;
+    a.flag = pl.flag;
     a.tap_off = pl.tap_off;
     a.m = pl.m;
     a.g = c->g;

@@ -220,6 +220,12 @@ __global__ void k_gather(const int32_t *__restrict__ perm, const T *__restrict__
     if (i < m) dst[i] = src[perm[i]];
 }
 
+// inv[perm[i]] = i (caller index -> sorted index)
+__global__ void k_invert(const int32_t *__restrict__ perm, int32_t *inv, int64_t m) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) inv[perm[i]] = (int32_t)i;
+}
+
 __global__ void k_iota(int32_t *x, int64_t m) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) x[i] = (int32_t)i;
@@ -767,9 +773,9 @@ void free_sorted_plan(Plan &pl) {
     void *ptrs[] = {pl.perm,   pl.ux,      pl.vx,         pl.weff,     pl.wt,
                     pl.jp,     pl.u0w,     pl.v0w,        pl.stack,    pl.sflag,
                     pl.tap_off, pl.border, pl.stats,      pl.ent,      pl.ent_off,
-                    pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole, pl.wrec};
+                    pl.ent_sorted, pl.item_start, pl.item_key, pl.item_sole, pl.wrec, pl.iperm};
     for (void *q : ptrs) dfree(q);
-    pl.perm = nullptr;
+    pl.perm = pl.iperm = nullptr;
     pl.ux = pl.vx = pl.weff = pl.wt = nullptr;
     pl.jp = pl.u0w = pl.v0w = pl.stack = pl.border = nullptr;
     pl.sflag = nullptr;
@@ -1512,7 +1518,9 @@ hipError_t make_plan(wsp_ctx *c, const double *d_centres, hipStream_t s, int *su
     WSP_STEP(dalloc(&pl.tap_off, m + 1));
     WSP_STEP(dalloc(&pl.border, m));
     WSP_STEP(dalloc(&pl.stats, 2));
+    WSP_STEP(dalloc(&pl.iperm, m));
     dim3 gb(grid1d(m, 256)), bb(256);
+    hipLaunchKernelGGL(k_invert, gb, bb, 0, s, pl.perm, pl.iperm, m);
     hipLaunchKernelGGL(k_gather<double>, gb, bb, 0, s, pl.perm, t.ux, pl.ux, m);
     hipLaunchKernelGGL(k_gather<double>, gb, bb, 0, s, pl.perm, t.vx, pl.vx, m);
     hipLaunchKernelGGL(k_gather<double>, gb, bb, 0, s, pl.perm, t.weff, pl.weff, m);

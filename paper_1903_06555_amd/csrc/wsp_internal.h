@@ -135,6 +135,7 @@ struct Plan {
     int32_t *label = nullptr;                           // stack
     // sorted order
     int32_t *perm = nullptr;      // sorted -> caller index
+    int32_t *iperm = nullptr;     // caller -> sorted index
     double *ux = nullptr;         // u/du - U0 (offset of the visibility from its first tap)
     double *vx = nullptr;
     double *weff = nullptr;       // w - wbar_k
