@@ -170,6 +170,40 @@ __device__ __forceinline__ void stockham_pass(C *sm, const C *__restrict__ tw, i
     __syncthreads();
 }
 
+// The first pass (radix 16, nothing combined yet) when the inputs in
+// [N/4, 3N/4) are zero and not read: butterfly j's inputs t = 4 .. 11 are
+// then zero, so its 16-point DFT splits (decimation in frequency) into two
+// 8-point DFTs of y_s = x_s + x_{s+8} and z_s = (x_s - x_{s+8}) e^{-+2 pi i s/16},
+// of which only one term is nonzero: X_{2m} = DFT8(y)_m, X_{2m+1} = DFT8(z)_m.
+template <bool kInv, int N, typename C>
+__device__ __forceinline__ void first_pass_half(C *sm, int tid) {
+    constexpr int NR = N / 16;
+    const int j = tid;
+    C y[8], z[8];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        y[s] = sm[lds_pos(j + s * NR)];
+        z[s] = rot16<kInv>(y[s], s);
+    }
+#pragma unroll
+    for (int s = 4; s < 8; ++s) {
+        y[s] = sm[lds_pos(j + (s + 8) * NR)];
+        z[s] = rot16<kInv>(y[s], s);
+        z[s].x = -z[s].x;
+        z[s].y = -z[s].y;
+    }
+    dft_reg<kInv, 8>(y);
+    dft_reg<kInv, 8>(z);
+    __syncthreads();
+    C *dst = sm + lds_pos(16 * j);  // 16 j .. 16 j + 15 share one pad slot offset
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        dst[2 * m] = y[m];
+        dst[2 * m + 1] = z[m];
+    }
+    __syncthreads();
+}
+
 template <int kLog, bool kInv, int kPass, typename C>
 __device__ __forceinline__ void fft_passes(C *sm, const C *__restrict__ tw, int tid) {
     constexpr int N = 1 << kLog, Ns = 1 << (4 * kPass);
@@ -187,6 +221,15 @@ __device__ __forceinline__ void fft_passes(C *sm, const C *__restrict__ tw, int 
 template <int kLog, bool kInv, typename C>
 __device__ __forceinline__ void lds_fft(C *sm, const C *__restrict__ tw, int tid) {
     fft_passes<kLog, kInv, 0>(sm, tw, tid);
+}
+
+// The same transform when the points in [N/4, 3N/4) are zero: they need not
+// be stored (a zero-padded half, as Z leaves it), and the first pass does
+// half the work.
+template <int kLog, bool kInv, typename C>
+__device__ __forceinline__ void lds_fft_half(C *sm, const C *__restrict__ tw, int tid) {
+    first_pass_half<kInv, 1 << kLog>(sm, tid);
+    fft_passes<kLog, kInv, 1>(sm, tw, tid);
 }
 
 // x, hidden from the optimiser: inside the per-stack loops, the transform's
@@ -271,9 +314,11 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_fwd(
                 sm[lds_pos(padded_of(j, g))] = z;
             }
         }
-        for (int V = h + tid; V < G - h; V += T) sm[lds_pos(V)] = zero;
+        // zeros where Z pads, except [G/4, 3G/4), which the first pass skips
+        for (int V = h + tid; V < G / 4; V += T) sm[lds_pos(V)] = zero;
+        for (int V = 3 * (G / 4) + tid; V < G - h; V += T) sm[lds_pos(V)] = zero;
         __syncthreads();
-        lds_fft<kLog, false>(sm, tw, opaque(tid));
+        lds_fft_half<kLog, false>(sm, tw, opaque(tid));
         C *dst = hp + ((int64_t)k * n + i) * n_used;
         for (int rr = tid; rr < n_used; rr += T) dst[rr] = sm[lds_pos(used_row(rr, g))];
         __syncthreads();
@@ -337,10 +382,11 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_fwd(
             const int i = t + q * T;
             if (i < n) sm[lds_pos(padded_of(i, g))] = pre[q];
         }
-        for (int U = h + t; U < G - h; U += T) sm[lds_pos(U)] = zero;
+        for (int U = h + t; U < G / 4; U += T) sm[lds_pos(U)] = zero;
+        for (int U = 3 * (G / 4) + t; U < G - h; U += T) sm[lds_pos(U)] = zero;
         if (rr + 1 < rr_end) fetch_pixels<T>(pre, tp + ((int64_t)k * n_used + rr + 1) * n, n, tid);
         __syncthreads();
-        lds_fft<kLog, false>(sm, tw, t);
+        lds_fft_half<kLog, false>(sm, tw, t);
         const int V = used_row(rr, g);
         C *dst = grids + ((int64_t)k * G + V) * G;
         const TileRow<G> trow(tiles + ((int64_t)k * (G / kTile) + V / kTile) * kTileWords<G>);
@@ -395,6 +441,8 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
     __shared__ C sm[G + G / 16];
     const int i = blockIdx.x, tid = threadIdx.x;
     const int n = g.n;
+    // used rows all outside [G/4, 3G/4): the first pass skips that half
+    const bool half = g.rows_lo <= G / 4 && g.rows_hi <= G / 4;
     double nm[kPix], acc[kPix];
 #pragma unroll
     for (int q = 0; q < kPix; ++q) {
@@ -422,10 +470,16 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
             if (rr < n_used) sm[lds_pos(used_row(rr, g))] = pre[q];
         }
         for (int rr = t + kPix * T; rr < n_used; rr += T) sm[lds_pos(used_row(rr, g))] = src[rr];
-        for (int V = g.rows_lo + t; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
+        if (half) {
+            for (int V = g.rows_lo + t; V < G / 4; V += T) sm[lds_pos(V)] = zero;
+            for (int V = 3 * (G / 4) + t; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
+        } else {
+            for (int V = g.rows_lo + t; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
+        }
         if (k + 1 < g.n_stacks) fetch_pixels<T>(pre, hp + ((int64_t)(k + 1) * n + i) * n_used, n_used, tid);
         __syncthreads();
-        lds_fft<kLog, true>(sm, tw, t);
+        if (half) lds_fft_half<kLog, true>(sm, tw, t);
+        else lds_fft<kLog, true>(sm, tw, t);
         const double ck = centres[k];
 #pragma unroll
         for (int q = 0; q < kPix; ++q) {
