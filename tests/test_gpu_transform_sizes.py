@@ -5,11 +5,15 @@ The LDS-resident transforms run for G = 2^m up to 8192 with N <= G / 2; their
 pass structure depends on G (radix-16 passes, then one of radix 2, 4 or 8, or
 none).  Grids of 64, 256, 512 and 1024 cells take the tails radix 4, none, 2
 and 4 (128, 2048, 4096 and 8192 are covered by the other operator tests);
+N = 80 on 256 cells leaves ragged 64 x 64 transpose tiles and N < G / 2;
 192 cells (a multiple of 64 that is not a power of two), and 64 cells with
 N = G, take the library passes.  Every visibility and every pixel is
 compared with the FP64 oracle, element by element against the largest
-output: FP64 path <= 1e-8 (the FP64 taps are within a few 1e-9 of the
-kernel peak), FP32 path <= 1e-5.  Three w-stacks with folding, so that the
+output: FP64 path <= 1e-7, FP32 path <= 1e-5.  The FP64 bar is set by the
+kernel taps, not the transforms (an indexing error would be of order one):
+their quadrature tolerance is 1e-6 of the peak, and they land within a few
+1e-9 at oversampling 2 and about 4e-8 at 3.2, where the integral of
+Eq. (6) runs to r = 1.6.  Three w-stacks with folding, so that the
 per-stack transforms and the stack sum are exercised.
 """
 import math
@@ -27,7 +31,7 @@ pytestmark = pytest.mark.gpu
 FOV = math.radians(10.0)
 
 # (n, oversample, transform path expected)
-CASES = [(32, 2.0, 1), (128, 2.0, 1), (256, 2.0, 1), (512, 2.0, 1), (96, 2.0, 0), (64, 1.0, 0)]
+CASES = [(32, 2.0, 1), (128, 2.0, 1), (256, 2.0, 1), (512, 2.0, 1), (80, 3.2, 1), (96, 2.0, 0), (64, 1.0, 0)]
 
 
 def max_rel(a, b):
@@ -47,13 +51,22 @@ def test_transforms_every_output(n, alpha, lds, precision):
     op = wsp.Operator(params, uvw, labels=ref.labels, centres=ref.centres)
     st = op.plan_stats()
     assert st["fft_lds"] == lds, (n, alpha, st["fft_lds"])
+    # the taps' own accuracy (the bar of the operator comparison below)
+    tap_err = 0.0
+    for p in range(0, ref.m, 10):
+        K, u0, v0 = op.kernel(p)
+        ru0, rv0, Kr = ref.kernel(p)
+        assert (u0, v0) == (ru0, rv0)
+        tap_err = max(tap_err, float(np.max(np.abs(K - Kr)) / np.max(np.abs(Kr))))
+    assert tap_err <= 1e-6
     x = syn.point_source_sky(n, 12, "exp", seed=n + 1)
     y = op.degrid(torch.from_numpy(x)).cpu().numpy()
     ey = max_rel(y, ref.forward(x))
     yin = syn.random_vis(ref.m, seed=n + 2)
     xa = op.grid(torch.from_numpy(yin)).cpu().numpy()
     ex = max_rel(xa, ref.adjoint(yin))
-    print(f"n {n} alpha {alpha} {precision} lds {lds} rows {st['fft_rows']}: degrid {ey:.2e} grid {ex:.2e}")
-    tol = 1e-8 if precision == "fp64" else 1e-5
+    print(f"n {n} alpha {alpha} {precision} lds {lds} rows {st['fft_rows']}: taps {tap_err:.2e} "
+          f"degrid {ey:.2e} grid {ex:.2e}")
+    tol = 1e-7 if precision == "fp64" else 1e-5
     assert ey <= tol and ex <= tol
     op.close()
