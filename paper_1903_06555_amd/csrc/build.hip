@@ -35,11 +35,17 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 // taps per lane of the tap kernel: fewer on the FP64 path, whose per-tap
-// state is twice as wide, so that more than one wavefront fits per SIMD
-template <bool kFP64>
+// state is twice as wide, so that more than one wavefront fits per SIMD;
+// and fewer when the visibilities have few points each (small supports:
+// most lanes' other slots would be idle, and fewer registers per lane let
+// more wavefronts hide the latency).  The per-point arithmetic is the same
+// either way.
+template <bool kFP64, bool kSmall>
 constexpr int taps_per_lane() {
-    return kFP64 ? 4 : 8;
+    return kSmall ? (kFP64 ? 1 : 2) : (kFP64 ? 4 : 8);
 }
+// mean points per visibility up to which the small variant runs
+constexpr int64_t kSmallTapsPerVis = 256;
 constexpr int kPanelGroup = 4;                 // panels per node batch (60 of 64 lanes)
 constexpr int kGroupNodes = kPanelGroup * WSP_GK_N;
 constexpr int64_t kBuildBatch = 65536;    // visibilities per partition batch
@@ -443,13 +449,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // taps_per_lane quadrature points); unit_off is the exclusive prefix of
 // chunks per visibility.  The points are the visibility's taps, or its
 // radial samples (then written, in FP64, to samples + samp_off[i]).
-template <bool kFP64>
+template <bool kFP64, bool kSmall>
 __global__ __launch_bounds__(256) void k_taps(BuildArgs A, int64_t batch0, int nb,
                                               const float *__restrict__ part,
                                               const int *__restrict__ npan,
                                               const int *__restrict__ unit_off, int nunits,
                                               double2 *samples, const int64_t *__restrict__ samp_off) {
-    constexpr int kTapsPerLane = taps_per_lane<kFP64>();
+    constexpr int kTapsPerLane = taps_per_lane<kFP64, kSmall>();
     const int lane = threadIdx.x & (kWave - 1);
     const int unit = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (unit >= nunits) return;
@@ -883,13 +889,15 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
         WSP_BSTEP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, uoff, B + 1, s));
         WSP_BSTEP(dmalloc(&tmp, tmp_bytes));
     }
+    const bool small = pl.total_taps <= kSmallTapsPerVis * pl.m;
     for (int64_t b0 = first; b0 < end; b0 += B) {
         int nb = (int)(end - b0 < B ? end - b0 : B);
         dim3 block(kWave * kWavesPerBlock);
         hipLaunchKernelGGL(k_partition, dim3((nb + kWavesPerBlock - 1) / kWavesPerBlock), block, 0,
                            s, A, b0, nb, part, npan);
-        const int64_t chunk = (int64_t)kWave * (c->p.precision == WSP_FP64 ? taps_per_lane<true>()
-                                                                           : taps_per_lane<false>());
+        const int64_t chunk =
+            (int64_t)kWave * (c->p.precision == WSP_FP64 ? (small ? taps_per_lane<true, true>() : taps_per_lane<true, false>())
+                                                         : (small ? taps_per_lane<false, true>() : taps_per_lane<false, false>()));
         hipLaunchKernelGGL(k_unit_counts, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, A, b0, nb,
                            chunk, cnt, scnt);
         WSP_BSTEP(hipGetLastError());
@@ -914,14 +922,22 @@ hipError_t run_build(wsp_ctx *c, const BuildArgs &A, int64_t first, int64_t coun
         }
         dim3 grid((unsigned)((nunits + kWavesPerBlock - 1) / kWavesPerBlock));
         if (c->p.precision == WSP_FP64) {
-            hipLaunchKernelGGL(k_taps<true>, grid, block, 0, s, A, b0, nb, part, npan, uoff, nunits,
-                               samples, soff);
+            if (small)
+                hipLaunchKernelGGL((k_taps<true, true>), grid, block, 0, s, A, b0, nb, part, npan, uoff, nunits,
+                                   samples, soff);
+            else
+                hipLaunchKernelGGL((k_taps<true, false>), grid, block, 0, s, A, b0, nb, part, npan, uoff, nunits,
+                                   samples, soff);
             if (nsamp > 0)
                 hipLaunchKernelGGL(k_interp<true>, dim3(nb), dim3(256), 0, s, A, b0,
                                    (const double2 *)samples, soff);
         } else {
-            hipLaunchKernelGGL(k_taps<false>, grid, block, 0, s, A, b0, nb, part, npan, uoff, nunits,
-                               samples, soff);
+            if (small)
+                hipLaunchKernelGGL((k_taps<false, true>), grid, block, 0, s, A, b0, nb, part, npan, uoff,
+                                   nunits, samples, soff);
+            else
+                hipLaunchKernelGGL((k_taps<false, false>), grid, block, 0, s, A, b0, nb, part, npan, uoff,
+                                   nunits, samples, soff);
             if (nsamp > 0)
                 hipLaunchKernelGGL(k_interp<false>, dim3(nb), dim3(256), 0, s, A, b0,
                                    (const double2 *)samples, soff);
