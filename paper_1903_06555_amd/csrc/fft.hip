@@ -430,8 +430,9 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
 // column hp[k][i][rr] placed at its used rows (zero elsewhere: rows without
 // work items hold no data) and transformed back along V; Z^dagger keeps the
 // pixel rows, S~_k^dagger and Re weight them, and the stacks are summed
-// (FP64 sum).  Output transposed: imageT[i][j].
-template <bool kFP64, int kLog>
+// (FP64 sum).  Output transposed: imageT[i][j].  kHalf: the used rows all
+// lie outside [G/4, 3G/4), whose points the first pass then skips.
+template <bool kFP64, int kLog, bool kHalf>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
     const typename Types<kFP64>::C *__restrict__ hp, typename Types<kFP64>::R *__restrict__ imageT,
     const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used) {
@@ -441,8 +442,6 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
     __shared__ C sm[G + G / 16];
     const int i = blockIdx.x, tid = threadIdx.x;
     const int n = g.n;
-    // used rows all outside [G/4, 3G/4): the first pass skips that half
-    const bool half = g.rows_lo <= G / 4 && g.rows_hi <= G / 4;
     double nm[kPix], acc[kPix];
 #pragma unroll
     for (int q = 0; q < kPix; ++q) {
@@ -470,7 +469,7 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
             if (rr < n_used) sm[lds_pos(used_row(rr, g))] = pre[q];
         }
         for (int rr = t + kPix * T; rr < n_used; rr += T) sm[lds_pos(used_row(rr, g))] = src[rr];
-        if (half) {
+        if constexpr (kHalf) {
             for (int V = g.rows_lo + t; V < G / 4; V += T) sm[lds_pos(V)] = zero;
             for (int V = 3 * (G / 4) + t; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
         } else {
@@ -478,7 +477,7 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
         }
         if (k + 1 < g.n_stacks) fetch_pixels<T>(pre, hp + ((int64_t)(k + 1) * n + i) * n_used, n_used, tid);
         __syncthreads();
-        if (half) lds_fft_half<kLog, true>(sm, tw, t);
+        if constexpr (kHalf) lds_fft_half<kLog, true>(sm, tw, t);
         else lds_fft<kLog, true>(sm, tw, t);
         const double ck = centres[k];
 #pragma unroll
@@ -678,8 +677,14 @@ struct Launch {
         static void run(const Geom &g, R *image, LdsBuffers<kFP64> b, const C *tw, const double *centres,
                         hipStream_t s) {
             const int used = g.rows_lo + g.rows_hi;
-            hipLaunchKernelGGL((k_fft_v_inv<kFP64, kLog>), dim3((unsigned)g.n), dim3(1u << (kLog - 4)), 0, s,
-                               (const C *)b.hp, b.imageT, tw, centres, g, used);
+            // kHalf: used rows all outside [G/4, 3G/4), so the first pass skips that half
+            const bool half = g.rows_lo <= (1 << kLog) / 4 && g.rows_hi <= (1 << kLog) / 4;
+            if (half)
+                hipLaunchKernelGGL((k_fft_v_inv<kFP64, kLog, true>), dim3((unsigned)g.n), dim3(1u << (kLog - 4)),
+                                   0, s, (const C *)b.hp, b.imageT, tw, centres, g, used);
+            else
+                hipLaunchKernelGGL((k_fft_v_inv<kFP64, kLog, false>), dim3((unsigned)g.n), dim3(1u << (kLog - 4)),
+                                   0, s, (const C *)b.hp, b.imageT, tw, centres, g, used);
             transpose_batch<R>(b.imageT, image, g.n, g.n, 1, s);
         }
     };
