@@ -1,6 +1,6 @@
 // F and F^dagger of the operator (Eqs. (4), (7)) as LDS-resident transforms
 // fused with the image-side steps, for grids of G = 2^m cells a side
-// (64 <= G <= 8192).
+// (64 <= G <= 8192) and N <= G / 2 pixels.
 //
 // The 2-D DFT of the zero-padded image is computed as G-point transforms
 // along V (grid rows) for every pixel column, then along U for every grid
@@ -11,15 +11,17 @@
 // into the same kernel:
 //   forward: S~_k, Z and the V transform of every stack from one read of an
 //            image column (k_fft_v_fwd); only the grid rows that hold work
-//            items are kept, transposed, and transformed along U straight
-//            into the grid (k_fft_u_fwd);
-//   inverse: the U transform of each used grid row, keeping the N columns
-//            that Z^dagger does not discard (k_fft_u_inv); transposed, then
-//            the V transform per pixel column with Z^dagger, S~_k^dagger, Re
-//            and the sum over stacks (k_fft_v_inv).
+//            items are kept, transposed, and transformed along U into the
+//            grid tiles that hold work items (k_fft_u_fwd);
+//   inverse: the U transform of each used grid row, reading only its used
+//            tiles and keeping the N columns that Z^dagger does not discard
+//            (k_fft_u_inv); transposed, then the V transform per pixel column
+//            with Z^dagger, S~_k^dagger, Re and the sum over stacks
+//            (k_fft_v_inv).
 // Against two library passes over the whole padded grid, with separate
-// taper, transpose and crop passes, this reads and writes the grid once per
-// used row and never materialises the padding.
+// taper, transpose and crop passes, this touches only the used rows and
+// tiles and never materialises the padding: where half of a transform's
+// input is zero (Z's padding), its first pass reads only the other half.
 #include <cmath>
 #include <vector>
 
