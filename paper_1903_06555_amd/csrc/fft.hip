@@ -14,9 +14,9 @@
 //            items are kept, transposed, and transformed along U into the
 //            grid tiles that hold work items (k_fft_u_fwd);
 //   inverse: the U transform of each used grid row, reading only its used
-//            tiles and keeping the N columns that Z^dagger does not discard
-//            (k_fft_u_inv); transposed, then the V transform per pixel column
-//            with Z^dagger, S~_k^dagger, Re and the sum over stacks
+//            tiles and keeping the N columns that Z^dagger does not discard,
+//            stored transposed (k_fft_u_inv); then the V transform per pixel
+//            column with Z^dagger, S~_k^dagger, Re and the sum over stacks
 //            (k_fft_v_inv).
 // Against two library passes over the whole padded grid, with separate
 // taper, transpose and crop passes, this touches only the used rows and
@@ -270,6 +270,18 @@ __device__ __forceinline__ int used_row(int rr, const Geom &g) {
     return rr < g.rows_lo ? rr : g.G - g.rows_hi + (rr - g.rows_lo);
 }
 
+// Work index of block b when the blocks of neighbouring indices should run
+// on one XCD (blocks are dealt to the 8 XCDs in turn): XCD b mod 8 takes the
+// (b mod 8)-th contiguous eighth of [0, n), in order.  A kernel whose blocks
+// each store a column of a matrix (8- or 16-byte elements a row apart) then
+// fills the cache lines of its neighbours in the same L2, which writes them
+// back whole.  The grid has 8 ceil(n / 8) blocks; -1 past n.
+__device__ __forceinline__ int xcd_index(int b, int n) {
+    const int per = (n + 7) / 8;
+    const int idx = (b % 8) * per + b / 8;
+    return idx < n ? idx : -1;
+}
+
 // Forward, first half.  Block: pixel column i.  For every stack k of [k0, k1),
 // sm[V] = S~_k Z x along column i (zero where Z pads), transformed along V;
 // the used rows go to hp[k][i][rr].  Pixel j of the column is thread
@@ -401,18 +413,21 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_fwd(
     }
 }
 
-// Inverse, first half.  Block: used-row slot rr of stack k.  Grid row V(rr)
-// (its used tiles; zero elsewhere) transformed back along U; the N pixel
-// columns go to tp[k][rr][i].
+// Inverse, first half.  Block: used-row slot rr of stack k (blocks in
+// xcd_index order over the nk n_used rows of stacks [k0, k0 + nk)).  Grid row
+// V(rr) (its used tiles; zero elsewhere) transformed back along U; the N
+// pixel columns go to row rr of hp[k][i][rr] (the layout the V pass reads).
 template <bool kFP64, int kLog>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
-    const typename Types<kFP64>::C *__restrict__ grids, typename Types<kFP64>::C *__restrict__ tp,
+    const typename Types<kFP64>::C *__restrict__ grids, typename Types<kFP64>::C *__restrict__ hp,
     const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used,
-    int k0) {
+    int k0, int nk) {
     using C = typename Types<kFP64>::C;
     constexpr int G = 1 << kLog, T = G / kPerThread;
     __shared__ C sm[G + G / 16];
-    const int rr = blockIdx.x, k = k0 + (int)blockIdx.y, tid = threadIdx.x;
+    const int row = xcd_index(blockIdx.x, nk * n_used);
+    if (row < 0) return;  // uniform over the block
+    const int k = k0 + row / n_used, rr = row % n_used, tid = threadIdx.x;
     const int n = g.n;
     C v[kPerThread];  // all loads in flight before the LDS stores
     fetch_row<G>(v, grids, tiles, k, used_row(rr, g), tid);
@@ -420,11 +435,11 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
     for (int q = 0; q < kPerThread; ++q) sm[lds_pos(tid + q * T)] = v[q];
     __syncthreads();
     lds_fft<kLog, true>(sm, tw, tid);
-    C *dst = tp + ((int64_t)k * n_used + rr) * n;
+    C *dst = hp + (int64_t)k * n * n_used + rr;
 #pragma unroll
     for (int q = 0; q < kPix; ++q) {
         const int i = tid + q * T;
-        if (i < n) dst[i] = sm[lds_pos(padded_of(i, g))];
+        if (i < n) dst[(int64_t)i * n_used] = sm[lds_pos(padded_of(i, g))];
     }
 }
 
@@ -668,10 +683,9 @@ struct Launch {
         static void run(const Geom &g, const C *grids, LdsBuffers<kFP64> b, const C *tw, const uint64_t *tiles,
                         int k0, int k1, hipStream_t s) {
             const int used = g.rows_lo + g.rows_hi, nk = k1 - k0;
-            hipLaunchKernelGGL((k_fft_u_inv<kFP64, kLog>), dim3((unsigned)used, (unsigned)nk),
-                               dim3(1u << (kLog - 4)), 0, s, grids, b.tp, tw, tiles, g, used, k0);
-            const int64_t off = (int64_t)k0 * g.n * used;
-            transpose_batch<C>(b.tp + off, b.hp + off, used, g.n, nk, s);
+            const int64_t rows = (int64_t)used * nk;
+            hipLaunchKernelGGL((k_fft_u_inv<kFP64, kLog>), dim3(8u * (unsigned)((rows + 7) / 8)),
+                               dim3(1u << (kLog - 4)), 0, s, grids, b.hp, tw, tiles, g, used, k0, nk);
         }
     };
     template <int kLog>
