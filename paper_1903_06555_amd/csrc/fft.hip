@@ -11,8 +11,9 @@
 // into the same kernel:
 //   forward: S~_k, Z and the V transform of every stack from one read of an
 //            image column (k_fft_v_fwd); only the grid rows that hold work
-//            items are kept, transposed, and transformed along U into the
-//            grid tiles that hold work items (k_fft_u_fwd);
+//            items are kept (a pixel's used rows contiguous), and read
+//            across pixels to be transformed along U into the grid tiles
+//            that hold work items (k_fft_u_fwd);
 //   inverse: the U transform of each used grid row, reading only its used
 //            tiles and keeping the N columns that Z^dagger does not discard,
 //            stored transposed (k_fft_u_inv); then the V transform per pixel
@@ -34,7 +35,7 @@ namespace {
 
 constexpr int kPerThread = 16;  // points per thread (radix-16 passes)
 constexpr int kPix = 8;         // pixels per thread along a column (N <= G / 2)
-constexpr int kURows = 4;       // grid rows per block of the forward U pass
+constexpr int kURows = 2;       // grid rows per block of the forward U pass
 constexpr int kTT = 64;         // transpose tile
 
 // LDS slot of point i: one pad slot after every 16 points, so that the
@@ -284,13 +285,13 @@ __device__ __forceinline__ int xcd_index(int b, int n) {
 
 // Forward, first half.  Block: pixel column i.  For every stack k of [k0, k1),
 // sm[V] = S~_k Z x along column i (zero where Z pads), transformed along V;
-// the used rows go to hp[k][i][rr].  Pixel j of the column is thread
-// j mod T's (q = j / T < 8, as N <= G / 2).
+// the used rows go to hp[k][i][rr] (rows ld apart).  Pixel j of the column
+// is thread j mod T's (q = j / T < 8, as N <= G / 2).
 template <bool kFP64, int kLog>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_fwd(
     const typename Types<kFP64>::R *__restrict__ imageT, typename Types<kFP64>::C *__restrict__ hp,
-    const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used, int k0,
-    int k1) {
+    const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used, int ld,
+    int k0, int k1) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     constexpr int G = 1 << kLog, T = G / kPerThread;
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_fwd(
         for (int V = 3 * (G / 4) + tid; V < G - h; V += T) sm[lds_pos(V)] = zero;
         __syncthreads();
         lds_fft_half<kLog, false>(sm, tw, opaque(tid));
-        C *dst = hp + ((int64_t)k * n + i) * n_used;
+        C *dst = hp + ((int64_t)k * n + i) * ld;
         for (int rr = tid; rr < n_used; rr += T) dst[rr] = sm[lds_pos(used_row(rr, g))];
         __syncthreads();
     }
@@ -368,37 +369,85 @@ __device__ __forceinline__ void fetch_row(C (&pre)[kPerThread], const C *__restr
     }
 }
 
-// Forward, second half.  Block: kURows used-row slots rr of stack k.  Row
-// V(rr) of the padded transform, from tp[k][rr][i] at the pixel columns
-// (zero where Z pads), transformed along U into the used tiles of the grid.
-// The next row's inputs are loaded while the current row is transformed.
+// The kURows consecutive used rows rr0 .. of the kPix pixels i = tid + q T
+// that thread tid holds (contiguous in hp; ld and rr0 are multiples of
+// kURows, so for FP32 they are one aligned 16-byte load).
+template <int T>
+__device__ __forceinline__ void fetch_rows(float2 (&pre)[kPix][kURows], const float2 *__restrict__ src, int ld,
+                                           int n, int tid) {
+    static_assert(kURows == 2, "one 16-byte load per pixel");
+#pragma unroll
+    for (int q = 0; q < kPix; ++q) {
+        const int i = tid + q * T;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < n) a = *(const float4 *)(src + (int64_t)i * ld);
+        pre[q][0] = make_float2(a.x, a.y);
+        pre[q][1] = make_float2(a.z, a.w);
+    }
+}
+template <int T>
+__device__ __forceinline__ void fetch_rows(double2 (&pre)[kPix][kURows], const double2 *__restrict__ src, int ld,
+                                           int n, int tid) {
+#pragma unroll
+    for (int q = 0; q < kPix; ++q) {
+        const int i = tid + q * T;
+#pragma unroll
+        for (int r = 0; r < kURows; ++r) {
+            pre[q][r] = make_double2(0.0, 0.0);
+            if (i < n) pre[q][r] = src[(int64_t)i * ld + r];
+        }
+    }
+}
+
+// pre[r] with r uniform but not a constant (selects, not a dynamically
+// indexed register array)
+template <typename C>
+__device__ __forceinline__ C pick_row(const C (&pre)[kURows], int r) {
+    C v = pre[0];
+#pragma unroll
+    for (int s = 1; s < kURows; ++s) {
+        v.x = r == s ? pre[s].x : v.x;
+        v.y = r == s ? pre[s].y : v.y;
+    }
+    return v;
+}
+
+// Forward, second half.  Block: kURows consecutive used-row slots rr of
+// stack k (blocks in xcd_index order over the row groups of stacks
+// [k0, k0 + nk)).  Row V(rr) of the padded transform, from hp[k][i][rr] at
+// the pixel columns (zero where Z pads), transformed along U into the used
+// tiles of the grid.  A pixel's kURows rows are contiguous in hp, so each
+// thread loads the group's rows of its pixels at once; the groups that
+// share cache lines run on one XCD at about the same time and find them in
+// its L2.
 template <bool kFP64, int kLog>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_fwd(
-    const typename Types<kFP64>::C *__restrict__ tp, typename Types<kFP64>::C *__restrict__ grids,
+    const typename Types<kFP64>::C *__restrict__ hp, typename Types<kFP64>::C *__restrict__ grids,
     const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used,
-    int k0) {
+    int ld, int k0, int nk) {
     using C = typename Types<kFP64>::C;
     constexpr int G = 1 << kLog, T = G / kPerThread;
     __shared__ C sm[G + G / 16];
-    const int k = k0 + (int)blockIdx.y, tid = threadIdx.x;
+    const int groups = (n_used + kURows - 1) / kURows;
+    const int grp = xcd_index(blockIdx.x, nk * groups);
+    if (grp < 0) return;  // uniform over the block
+    const int k = k0 + grp / groups, rr0 = (grp % groups) * kURows, tid = threadIdx.x;
     const int n = g.n, h = n / 2;
-    const int rr0 = blockIdx.x * kURows;
     const int rr_end = rr0 + kURows < n_used ? rr0 + kURows : n_used;
     C zero;
     zero.x = 0;
     zero.y = 0;
-    C pre[kPix];
-    fetch_pixels<T>(pre, tp + ((int64_t)k * n_used + rr0) * n, n, tid);
+    C pre[kPix][kURows];
+    fetch_rows<T>(pre, hp + (int64_t)k * n * ld + rr0, ld, n, tid);
     for (int rr = rr0; rr < rr_end; ++rr) {
         const int t = opaque(tid);
 #pragma unroll
         for (int q = 0; q < kPix; ++q) {
             const int i = t + q * T;
-            if (i < n) sm[lds_pos(padded_of(i, g))] = pre[q];
+            if (i < n) sm[lds_pos(padded_of(i, g))] = pick_row(pre[q], rr - rr0);
         }
         for (int U = h + t; U < G / 4; U += T) sm[lds_pos(U)] = zero;
         for (int U = 3 * (G / 4) + t; U < G - h; U += T) sm[lds_pos(U)] = zero;
-        if (rr + 1 < rr_end) fetch_pixels<T>(pre, tp + ((int64_t)k * n_used + rr + 1) * n, n, tid);
         __syncthreads();
         lds_fft_half<kLog, false>(sm, tw, t);
         const int V = used_row(rr, g);
@@ -421,7 +470,7 @@ template <bool kFP64, int kLog>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
     const typename Types<kFP64>::C *__restrict__ grids, typename Types<kFP64>::C *__restrict__ hp,
     const typename Types<kFP64>::C *__restrict__ tw, const uint64_t *__restrict__ tiles, Geom g, int n_used,
-    int k0, int nk) {
+    int ld, int k0, int nk) {
     using C = typename Types<kFP64>::C;
     constexpr int G = 1 << kLog, T = G / kPerThread;
     __shared__ C sm[G + G / 16];
@@ -435,11 +484,11 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
     for (int q = 0; q < kPerThread; ++q) sm[lds_pos(tid + q * T)] = v[q];
     __syncthreads();
     lds_fft<kLog, true>(sm, tw, tid);
-    C *dst = hp + (int64_t)k * n * n_used + rr;
+    C *dst = hp + (int64_t)k * n * ld + rr;
 #pragma unroll
     for (int q = 0; q < kPix; ++q) {
         const int i = tid + q * T;
-        if (i < n) dst[(int64_t)i * n_used] = sm[lds_pos(padded_of(i, g))];
+        if (i < n) dst[(int64_t)i * ld] = sm[lds_pos(padded_of(i, g))];
     }
 }
 
@@ -452,7 +501,8 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_u_inv(
 template <bool kFP64, int kLog, bool kHalf>
 __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
     const typename Types<kFP64>::C *__restrict__ hp, typename Types<kFP64>::R *__restrict__ imageT,
-    const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used) {
+    const typename Types<kFP64>::C *__restrict__ tw, const double *__restrict__ centres, Geom g, int n_used,
+    int ld) {
     using R = typename Types<kFP64>::R;
     using C = typename Types<kFP64>::C;
     constexpr int G = 1 << kLog, T = G / kPerThread;
@@ -476,10 +526,10 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
     // the first kPix T used rows of the next stack's column are loaded while
     // the current stack is transformed
     C pre[kPix];
-    fetch_pixels<T>(pre, hp + (int64_t)i * n_used, n_used, tid);
+    fetch_pixels<T>(pre, hp + (int64_t)i * ld, n_used, tid);
     for (int k = 0; k < g.n_stacks; ++k) {
         const int t = opaque(tid);
-        const C *src = hp + ((int64_t)k * n + i) * n_used;
+        const C *src = hp + ((int64_t)k * n + i) * ld;
 #pragma unroll
         for (int q = 0; q < kPix; ++q) {
             const int rr = t + q * T;
@@ -492,7 +542,7 @@ __global__ __launch_bounds__(1 << (kLog - 4), kFP64 ? 2 : 4) void k_fft_v_inv(
         } else {
             for (int V = g.rows_lo + t; V < G - g.rows_hi; V += T) sm[lds_pos(V)] = zero;
         }
-        if (k + 1 < g.n_stacks) fetch_pixels<T>(pre, hp + ((int64_t)(k + 1) * n + i) * n_used, n_used, tid);
+        if (k + 1 < g.n_stacks) fetch_pixels<T>(pre, hp + ((int64_t)(k + 1) * n + i) * ld, n_used, tid);
         __syncthreads();
         if constexpr (kHalf) lds_fft_half<kLog, true>(sm, tw, t);
         else lds_fft<kLog, true>(sm, tw, t);
@@ -614,32 +664,36 @@ hipError_t fft_lds_twiddles(int G, bool fp64, void *dev) {
     return hipMemcpy(dev, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice);
 }
 
-// Scratch of the LDS transforms: hp [K][N][n_used], tp [K][n_used][N], then
-// the transposed image imageT [N][N] (the forward's input, the adjoint's
-// output).
+// Row stride of hp: the used rows, rounded up to whole row groups of the
+// forward U pass.
+static int hp_ld(const Geom &g) { return (g.rows_lo + g.rows_hi + kURows - 1) / kURows * kURows; }
+
+static size_t hp_bytes(const Geom &g, bool fp64) {
+    return ((size_t)g.n_stacks * g.n * hp_ld(g) * (fp64 ? 16 : 8) + 255) & ~(size_t)255;
+}
+
+// Scratch of the LDS transforms: hp [K][N][ld] (a pixel column's used rows,
+// between the two passes of either direction), then the transposed image
+// imageT [N][N] (the forward's input, the adjoint's output).
 size_t fft_lds_scratch_bytes(const Geom &g, bool fp64) {
-    const size_t cb = fp64 ? 16 : 8, rb = fp64 ? 8 : 4;
-    const size_t used = (size_t)(g.rows_lo + g.rows_hi);
-    const size_t half = ((size_t)g.n_stacks * g.n * used * cb + 255) & ~(size_t)255;
-    return 2 * half + (size_t)g.n * g.n * rb;
+    return hp_bytes(g, fp64) + (size_t)g.n * g.n * (fp64 ? 8 : 4);
 }
 
 namespace {
 
 template <bool kFP64>
 struct LdsBuffers {
-    typename Types<kFP64>::C *hp, *tp;
+    typename Types<kFP64>::C *hp;
     typename Types<kFP64>::R *imageT;
 };
 
 template <bool kFP64>
 LdsBuffers<kFP64> lds_buffers(const Geom &g, void *scratch) {
     using C = typename Types<kFP64>::C;
-    const size_t half = ((size_t)g.n_stacks * g.n * (g.rows_lo + g.rows_hi) * sizeof(C) + 255) & ~(size_t)255;
+    const size_t half = hp_bytes(g, kFP64);
     LdsBuffers<kFP64> b;
     b.hp = (C *)scratch;
-    b.tp = (C *)((char *)scratch + half);
-    b.imageT = (typename Types<kFP64>::R *)((char *)scratch + 2 * half);
+    b.imageT = (typename Types<kFP64>::R *)((char *)scratch + half);
     return b;
 }
 
@@ -667,15 +721,13 @@ struct Launch {
     struct Forward {
         static void run(const Geom &g, C *grids, LdsBuffers<kFP64> b, const C *tw, const uint64_t *tiles,
                         const double *centres, int k0, int k1, hipStream_t s) {
-            const int used = g.rows_lo + g.rows_hi, nk = k1 - k0;
+            const int used = g.rows_lo + g.rows_hi, nk = k1 - k0, ld = hp_ld(g);
             const dim3 bd(1u << (kLog - 4));
             hipLaunchKernelGGL((k_fft_v_fwd<kFP64, kLog>), dim3((unsigned)g.n), bd, 0, s, (const R *)b.imageT,
-                               b.hp, tw, centres, g, used, k0, k1);
-            const int64_t off = (int64_t)k0 * g.n * used;
-            transpose_batch<C>(b.hp + off, b.tp + off, g.n, used, nk, s);
-            const dim3 gu((unsigned)((used + kURows - 1) / kURows), (unsigned)nk);
-            hipLaunchKernelGGL((k_fft_u_fwd<kFP64, kLog>), gu, bd, 0, s, (const C *)b.tp, grids, tw, tiles, g,
-                               used, k0);
+                               b.hp, tw, centres, g, used, ld, k0, k1);
+            const int64_t groups = (int64_t)nk * ((used + kURows - 1) / kURows);
+            hipLaunchKernelGGL((k_fft_u_fwd<kFP64, kLog>), dim3(8u * (unsigned)((groups + 7) / 8)), bd, 0, s,
+                               (const C *)b.hp, grids, tw, tiles, g, used, ld, k0, nk);
         }
     };
     template <int kLog>
@@ -685,7 +737,8 @@ struct Launch {
             const int used = g.rows_lo + g.rows_hi, nk = k1 - k0;
             const int64_t rows = (int64_t)used * nk;
             hipLaunchKernelGGL((k_fft_u_inv<kFP64, kLog>), dim3(8u * (unsigned)((rows + 7) / 8)),
-                               dim3(1u << (kLog - 4)), 0, s, grids, b.hp, tw, tiles, g, used, k0, nk);
+                               dim3(1u << (kLog - 4)), 0, s, grids, b.hp, tw, tiles, g, used, hp_ld(g), k0,
+                               nk);
         }
     };
     template <int kLog>
@@ -697,10 +750,12 @@ struct Launch {
             const bool half = g.rows_lo <= (1 << kLog) / 4 && g.rows_hi <= (1 << kLog) / 4;
             if (half)
                 hipLaunchKernelGGL((k_fft_v_inv<kFP64, kLog, true>), dim3((unsigned)g.n), dim3(1u << (kLog - 4)),
-                                   0, s, (const C *)b.hp, b.imageT, tw, centres, g, used);
+                                   0, s, (const C *)b.hp, b.imageT, tw, centres, g, used,
+                                   hp_ld(g));
             else
                 hipLaunchKernelGGL((k_fft_v_inv<kFP64, kLog, false>), dim3((unsigned)g.n), dim3(1u << (kLog - 4)),
-                                   0, s, (const C *)b.hp, b.imageT, tw, centres, g, used);
+                                   0, s, (const C *)b.hp, b.imageT, tw, centres, g, used,
+                                   hp_ld(g));
             transpose_batch<R>(b.imageT, image, g.n, g.n, 1, s);
         }
     };
