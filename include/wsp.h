@@ -156,9 +156,12 @@ typedef struct wsp_ctx wsp_ctx;
  * tolerance 1e-3 and 100 iterations, device 0.  n and fov_rad are left 0. */
 void wsp_default_params(wsp_params *p);
 
-/* Validate *p and create a context on p->device.  Makes the batched 1-D FFT
- * plans of length G = alpha N that carry F and F^dagger of the K stacks as
- * passes along v and u (their work area lives in the caller's scratch).
+/* Validate *p and create a context on p->device.  F and F^dagger of the K
+ * stacks run as G-point transforms along v and u, G = alpha N: for G a power
+ * of two from 64 to 8192 with N <= G / 2 (and the transform's workgroup
+ * within the device's LDS), as LDS-resident transforms whose twiddle table
+ * is uploaded here; otherwise as batched 1-D library FFT plans made here.
+ * Their work area lives in the caller's scratch.
  * Errors: WSP_EINVAL (parameters), WSP_EHIP. */
 wsp_status wsp_create(const wsp_params *p, wsp_ctx **out);
 
