@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kPerThread = 16;  // points per thread (radix-16 passes)
 constexpr int kPix = 8;         // pixels per thread along a column (N <= G / 2)
-constexpr int kURows = 2;       // grid rows per block of the forward U pass
+constexpr int kURows = 2;       // grid rows per block of the forward U pass (the adjoint U pass takes pairs too)
 constexpr int kTT = 64;         // transpose tile
 
 // LDS slot of point i: one pad slot after every 16 points, so that the
